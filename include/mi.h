@@ -1,0 +1,142 @@
+/*
+ * mi.h -- all-pairs mutual information of a binary dataset on an MI355X GPU.
+ *
+ * The operation (paper Section 1, Eq. 1, unrolled in Eq. 2/3): for an m x n
+ * binary matrix X (rows are samples, columns are variables, Section 2 step 1)
+ * compute for every column pair (i, j)
+ *
+ *     MI_ij = sum_{x,y in {0,1}} p(x,y) log2( p(x,y) / (p(x) p(y)) )   [bits]
+ *
+ * the matrix way: one Gram product n11 = X^T X (Section 2 step 2, Section 3),
+ * column sums c = diag(n11) (Section 2 step 3, Section 3.1 "Term 2"), and the
+ * other joint counts derived without further products (Section 3.1, Eq. 6
+ * and Eq. 7, orientation taken from first principles):
+ *
+ *     n10 = c_i - n11,   n01 = c_j - n11,   n00 = m - c_i - c_j + n11.
+ *
+ * A cell with n_xy = 0 contributes exactly 0 (0 log 0 = 0); the paper's
+ * unspecified epsilon (Section 2 step 5) is not used.  The diagonal holds
+ * H(X_i).  Counts are exact (int8 x int8 -> int32 matrix cores); MI is
+ * evaluated in FP32, optionally recomputed in FP64 (see mi_epilogue).
+ *
+ * Conventions for every entry point:
+ *   - Data pointers are DEVICE pointers on the current HIP device.  The
+ *     caller owns them; the library never frees them.  They must stay valid
+ *     until the work completes (stream order, or ticket completion for the
+ *     server).
+ *   - X is row-major, m rows of ldx >= n bytes; entries must be 0 or 1
+ *     (other values give undefined results unless `validate` is set).  Bytes
+ *     in columns [n, ldx) are ignored.  The fast load path is taken when X is
+ *     16-byte aligned and ldx is a multiple of 16; other layouts are correct
+ *     but slower.
+ *   - out is n x n FP32, row-major, the full symmetric matrix (both
+ *     triangles are written; out[i][j] and out[j][i] are bitwise equal).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Nothing is thrown across the ABI: every call returns an mi_status and
+ *     mi_last_error() gives a thread-local message for the last failure.
+ *   - Limits: 1 <= m <= 2^31 - 1 (int32 counts), 0 <= n <= 2^31 - 1; n == 0
+ *     is a successful no-op.  Counts convert exactly to FP32 below 2^24 rows;
+ *     above that the FP32 epilogue rounds them (the FP64 modes stay exact).
+ */
+#ifndef MI_H_
+#define MI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mi_status {
+  MI_OK = 0,
+  MI_ERR_INVALID_ARG = 1,   /* bad size, NULL pointer, bad enum value        */
+  MI_ERR_NOT_BINARY = 2,    /* validate != 0 and X holds a byte other than 0/1 */
+  MI_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed                    */
+  MI_ERR_BUDGET = 4,        /* server: request alone exceeds the HBM budget   */
+  MI_ERR_QUEUE_FULL = 5,    /* server: bounded queue is full                  */
+  MI_ERR_NOT_READY = 6,     /* server: ticket not finished yet (poll)         */
+  MI_ERR_DEVICE = 7,        /* a HIP call failed                              */
+  MI_ERR_TIMEOUT = 8,       /* server: wait timed out                         */
+  MI_ERR_UNKNOWN_TICKET = 9 /* server: ticket was never issued or already collected */
+} mi_status;
+
+/* How MI is evaluated from the exact counts (the counts are always exact). */
+typedef enum mi_epilogue {
+  MI_EPI_FP32 = 0,               /* FP32 log2 per cell                                    */
+  MI_EPI_FP32_FP64_FALLBACK = 1, /* FP32, recomputed in FP64 where the FP32 MI < tau       */
+  MI_EPI_FP64 = 2                /* FP64 for every pair (rounded to FP32 on output)        */
+} mi_epilogue;
+
+/* Tile configurations of the fused kernel (0 = let the library choose). */
+typedef enum mi_tile {
+  MI_TILE_AUTO = 0,
+  MI_TILE_128 = 1,  /* 128 x 128 output tile, 4 waves of 64 x 64 */
+  MI_TILE_256 = 2   /* 256 x 256 output tile, 4 waves of 128 x 128 */
+} mi_tile;
+
+typedef struct mi_problem {
+  const uint8_t* X;      /* device, m x ldx bytes, row-major, 0/1                   */
+  int64_t m;             /* rows (samples), >= 1                                    */
+  int64_t n;             /* columns (variables), >= 0                               */
+  int64_t ldx;           /* row pitch in bytes, >= n; 0 means n                     */
+  float* out;            /* device, n x n FP32 row-major (required when n > 0)      */
+  int32_t* n11_out;      /* optional device n x n int32: the 1-1 counts X^T X        */
+  int32_t* colsum_out;   /* optional device int32[n]: column sums c                 */
+  int32_t epilogue;      /* mi_epilogue                                             */
+  float fallback_tau;    /* MI_EPI_FP32_FP64_FALLBACK threshold in bits; <= 0: 1e-3  */
+  int32_t validate;      /* nonzero: check X is 0/1 first (one extra pass, blocking) */
+  int32_t tile;          /* mi_tile; 0 = autotuned / heuristic                      */
+  int32_t splits;        /* K-splits over the rows; 0 = autotuned / heuristic       */
+} mi_problem;
+
+/* Fill *p with defaults for X (m x n, ldx = n) and out: FP32 epilogue, auto config. */
+void mi_problem_init(mi_problem* p, const uint8_t* X, int64_t m, int64_t n, float* out);
+
+/* Blocking: computes out on the default stream and synchronises it. */
+mi_status mi_all_pairs(const uint8_t* X, int64_t m, int64_t n, float* out);
+
+/* Asynchronous on `stream`; returns once the work is enqueued. */
+mi_status mi_all_pairs_async(const uint8_t* X, int64_t m, int64_t n, float* out, void* stream);
+
+/* Full control (pitch, counts export, epilogue mode, config).  Asynchronous on
+ * `stream` unless p->validate is set (then it synchronises to read the check). */
+mi_status mi_all_pairs_ex(const mi_problem* p, void* stream);
+
+/* Many independent datasets in one call, asynchronous on `stream`.
+ *   mode MI_BATCH_PERSISTENT: one persistent launch per tile configuration
+ *        pulls (dataset, tile, split) work units from a device queue;
+ *   mode MI_BATCH_GRAPH: `count` plain launches captured once into a hipGraph
+ *        and replayed (the graph is cached for identical batches);
+ *   mode MI_BATCH_SEQUENTIAL: `count` plain launches, one after another.
+ * All three give bitwise identical outputs.  validate is not allowed here. */
+typedef enum mi_batch_mode {
+  MI_BATCH_PERSISTENT = 0,
+  MI_BATCH_GRAPH = 1,
+  MI_BATCH_SEQUENTIAL = 2
+} mi_batch_mode;
+mi_status mi_all_pairs_batched(const mi_problem* probs, int64_t count, void* stream, int32_t mode);
+
+/* Configuration the library would use for an (m, n, ldx) problem. */
+mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits);
+
+/* Autotuner: time the candidate (tile, splits) configurations for this shape
+ * on the current device (on a scratch zero matrix: the kernel's time does not
+ * depend on the data) and remember the fastest for every later call with the
+ * same shape class.  *best_ms receives its time (may be NULL). */
+mi_status mi_tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms);
+mi_status mi_tuner_save(const char* path);   /* JSON lines */
+mi_status mi_tuner_load(const char* path);
+void mi_tuner_clear(void);
+
+/* Thread-local message describing the last failure on the calling thread. */
+const char* mi_last_error(void);
+
+/* Library version string. */
+const char* mi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI_H_ */

@@ -1,0 +1,701 @@
+// mi_api.hip -- the C ABI (include/mi.h): argument checks, planning, the
+// split-K workspace, the batched modes and the autotuner.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mi.h"
+#include "mi_internal.hpp"
+#include "mi_host.hpp"
+
+namespace mi {
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string g_err;
+
+mi_status fail(mi_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+void clear_error() { g_err.clear(); }
+const char* last_error() { return g_err.c_str(); }
+
+// ------------------------------------------------------------- device info --
+static std::mutex g_info_mu;
+static std::map<int, DeviceInfo> g_info;
+
+mi_status device_info(DeviceInfo* out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_info_mu);
+  auto it = g_info.find(dev);
+  if (it == g_info.end()) {
+    DeviceInfo di;
+    di.device = dev;
+    HIPCHK(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    di.occ[0] = occupancy(128);
+    di.occ[1] = occupancy(256);
+    di.pocc[0] = persistent_occupancy(128);
+    di.pocc[1] = persistent_occupancy(256);
+    it = g_info.emplace(dev, di).first;
+  }
+  *out = it->second;
+  return MI_OK;
+}
+
+// --------------------------------------------------------------- workspace --
+// Split-K needs zeroed int32 scratch per tile.  Kernels leave it zeroed again,
+// so a buffer is cleared only when it is (re)allocated.  Buffers are keyed by
+// (device, stream, slot): work on one stream is ordered, so reuse is safe.
+struct WsKey {
+  int dev;
+  hipStream_t st;
+  int slot;
+  bool operator<(const WsKey& o) const { return std::tie(dev, st, slot) < std::tie(o.dev, o.st, o.slot); }
+};
+struct WsBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+static std::mutex g_ws_mu;
+static std::map<WsKey, WsBuf> g_ws;
+
+mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) return MI_OK;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  WsBuf& w = g_ws[WsKey{dev, st, slot}];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    const size_t sz = std::max(bytes, (size_t)1 << 20);
+    if (hipMalloc(&w.ptr, sz) != hipSuccess) {
+      (void)hipGetLastError();
+      w.ptr = nullptr;
+      return fail(MI_ERR_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed", sz);
+    }
+    HIPCHK(hipMemset(w.ptr, 0, sz));
+    w.bytes = sz;
+  }
+  *out = w.ptr;
+  return MI_OK;
+}
+
+// ----------------------------------------------------------------- planner --
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t workspace_bytes(const Plan& pl) {
+  if (pl.splits <= 1) return 0;
+  const int64_t per = (int64_t)pl.bt * pl.bt + 2 * pl.bt + 1;
+  return (size_t)(pl.ntiles * per * sizeof(int32_t) + 256);
+}
+
+Plan make_plan(int64_t m, int64_t n, int bt, int splits) {
+  Plan pl;
+  pl.bt = bt;
+  pl.ntp = (int)cdiv(n, bt);
+  pl.ntiles = pl.ntp * (pl.ntp + 1) / 2;
+  const int64_t steps = cdiv(m, KT);
+  if (splits < 1) splits = 1;
+  if (splits > steps) splits = (int)steps;
+  const int64_t per = cdiv(steps, splits);
+  pl.kchunk = (int)(per * KT);
+  pl.splits = (int)cdiv(m, pl.kchunk);
+  return pl;
+}
+
+// Heuristic when the tuner has no entry: enough units to fill every slot of
+// the chip in whole waves, with at least kMinRows rows per split so that the
+// workspace flush stays small next to the streamed panels.
+static int heuristic_splits(int64_t m, int ntiles, int slots) {
+  const int64_t kMinRows = 2048;
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(256, m / kMinRows));
+  int best = 1;
+  double best_eff = 0.0;
+  for (int64_t s = 1; s <= smax; ++s) {
+    const double units = (double)ntiles * (double)s;
+    const double waves = std::ceil(units / slots);
+    const double eff = units / (waves * slots);
+    if (eff > best_eff + 0.02) {
+      best_eff = eff;
+      best = (int)s;
+    }
+    if (eff > 0.97) break;
+  }
+  return best;
+}
+
+static int heuristic_tile(int64_t m, int64_t n) {
+  (void)m;
+  (void)n;
+  return 128;
+}
+
+// Tuned entries, keyed by a shape class: m in quarter octaves, n in 64-column
+// steps, and whether the fast aligned load path applies.
+struct ShapeKey {
+  int mb, nb, aligned;
+  bool operator<(const ShapeKey& o) const { return std::tie(mb, nb, aligned) < std::tie(o.mb, o.nb, o.aligned); }
+};
+struct Tuned {
+  int bt, splits;
+  double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<ShapeKey, Tuned> g_tuned;
+
+static ShapeKey shape_key(int64_t m, int64_t n, bool aligned) {
+  ShapeKey k;
+  k.mb = (int)std::lround(4.0 * std::log2((double)std::max<int64_t>(m, 1)));
+  k.nb = (int)cdiv(n, 64);
+  k.aligned = aligned ? 1 : 0;
+  return k;
+}
+
+mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out) {
+  DeviceInfo di;
+  mi_status s = device_info(&di);
+  if (s != MI_OK) return s;
+  int bt = tile_req == MI_TILE_256 ? 256 : (tile_req == MI_TILE_128 ? 128 : 0);
+  int splits = splits_req;
+  if (bt == 0 || splits <= 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(shape_key(m, n, aligned));
+    if (it != g_tuned.end()) {
+      if (bt == 0) bt = it->second.bt;
+      if (splits <= 0 && bt == it->second.bt) splits = it->second.splits;
+    }
+  }
+  if (bt == 0) bt = heuristic_tile(m, n);
+  if (splits <= 0) {
+    const Plan p1 = make_plan(m, n, bt, 1);
+    splits = heuristic_splits(m, p1.ntiles, di.cus * di.occ[bt == 256 ? 1 : 0]);
+  }
+  *out = make_plan(m, n, bt, splits);
+  return MI_OK;
+}
+
+// -------------------------------------------------------------- arguments --
+mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
+  if (!p) return fail(MI_ERR_INVALID_ARG, "problem is NULL");
+  if (p->m <= 0) return fail(MI_ERR_INVALID_ARG, "m must be >= 1 (got %lld)", (long long)p->m);
+  if (p->m > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "m must be <= 2^31-1 (int32 counts), got %lld", (long long)p->m);
+  if (p->n < 0) return fail(MI_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)p->n);
+  if (p->n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "n must be <= 2^31-1");
+  const int64_t ldx = p->ldx == 0 ? p->n : p->ldx;
+  if (ldx < p->n) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)p->n);
+  if (p->n > 0 && (!p->X || !p->out)) return fail(MI_ERR_INVALID_ARG, "X and out must be non-NULL when n > 0");
+  if (p->epilogue < 0 || p->epilogue > 2) return fail(MI_ERR_INVALID_ARG, "bad epilogue mode %d", p->epilogue);
+  if (p->tile < 0 || p->tile > 2) return fail(MI_ERR_INVALID_ARG, "bad tile id %d", p->tile);
+  if (p->splits < 0) return fail(MI_ERR_INVALID_ARG, "splits must be >= 0");
+  *ldx_out = ldx;
+  return MI_OK;
+}
+
+bool is_aligned(const uint8_t* X, int64_t ldx) { return ((uintptr_t)X % 16 == 0) && (ldx % 16 == 0); }
+
+ProbDev make_probdev(const mi_problem* p, int64_t ldx, const Plan& pl, void* ws) {
+  ProbDev P;
+  std::memset(&P, 0, sizeof P);
+  P.X = p->X;
+  P.ldx = ldx;
+  P.m = (int32_t)p->m;
+  P.n = (int32_t)p->n;
+  P.out = p->out;
+  P.n11_out = p->n11_out;
+  P.colsum_out = p->colsum_out;
+  P.ntp = pl.ntp;
+  P.ntiles = pl.ntiles;
+  P.splits = pl.splits;
+  P.kchunk = pl.kchunk;
+  P.epi = p->epilogue;
+  P.tau = p->fallback_tau > 0.0f ? p->fallback_tau : 1e-3f;
+  P.aligned = is_aligned(p->X, ldx) ? 1 : 0;
+  if (pl.splits > 1 && ws) {
+    int32_t* base = reinterpret_cast<int32_t*>(ws);
+    P.ws_n11 = base;
+    P.ws_col = base + (int64_t)pl.ntiles * pl.bt * pl.bt;
+    P.counters = P.ws_col + (int64_t)pl.ntiles * 2 * pl.bt;
+  }
+  return P;
+}
+
+static std::mutex g_flag_mu;
+static std::map<int, int*> g_flag;
+
+mi_status validate_binary(const mi_problem* p, int64_t ldx, hipStream_t st) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int* flag = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    int*& f = g_flag[dev];
+    if (!f) HIPCHK(hipMalloc(&f, 256));
+    flag = f;
+  }
+  HIPCHK(launch_validate(p->X, p->m, p->n, ldx, flag, st));
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h) return fail(MI_ERR_NOT_BINARY, "X holds a byte other than 0 or 1");
+  return MI_OK;
+}
+
+mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot) {
+  int64_t ldx = 0;
+  mi_status s = check_problem(p, &ldx);
+  if (s != MI_OK) return s;
+  if (p->n == 0) return MI_OK;
+  if (p->validate) {
+    s = validate_binary(p, ldx, st);
+    if (s != MI_OK) return s;
+  }
+  Plan pl;
+  s = choose_plan(p->m, p->n, is_aligned(p->X, ldx), p->tile, p->splits, &pl);
+  if (s != MI_OK) return s;
+  void* ws = nullptr;
+  s = workspace(st, ws_slot, workspace_bytes(pl), &ws);
+  if (s != MI_OK) return s;
+  const ProbDev P = make_probdev(p, ldx, pl, ws);
+  HIPCHK(launch_plain(pl.bt, P, st));
+  return MI_OK;
+}
+
+// ----------------------------------------------------------------- batched --
+struct BatchBufs {
+  void* dev = nullptr;  // ProbDev[count] + UnitRef[units] + heads
+  size_t dev_bytes = 0;
+  void* host = nullptr;  // pinned staging
+  size_t host_bytes = 0;
+  hipEvent_t copied = nullptr;
+};
+static std::mutex g_batch_mu;
+static std::map<std::pair<int, hipStream_t>, BatchBufs> g_batch;
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+};
+static std::mutex g_graph_mu;
+static std::map<std::string, GraphEntry> g_graphs;
+
+static std::string batch_key(const mi_problem* probs, int64_t count, const std::vector<Plan>& plans, hipStream_t st) {
+  std::string k;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%p|%lld|", (void*)st, (long long)count);
+  k += buf;
+  for (int64_t d = 0; d < count; ++d) {
+    const mi_problem& p = probs[d];
+    snprintf(buf, sizeof buf, "%p,%lld,%lld,%lld,%p,%p,%p,%d,%g,%d,%d;", (const void*)p.X, (long long)p.m,
+             (long long)p.n, (long long)p.ldx, (void*)p.out, (void*)p.n11_out, (void*)p.colsum_out, p.epilogue,
+             (double)p.fallback_tau, plans[d].bt, plans[d].splits);
+    k += buf;
+  }
+  return k;
+}
+
+mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode) {
+  if (count < 0) return fail(MI_ERR_INVALID_ARG, "count < 0");
+  if (count == 0) return MI_OK;
+  if (!probs) return fail(MI_ERR_INVALID_ARG, "probs is NULL");
+  if (mode < 0 || mode > 2) return fail(MI_ERR_INVALID_ARG, "bad batch mode %d", mode);
+  if (count > INT32_MAX / 4) return fail(MI_ERR_INVALID_ARG, "count too large");
+  std::vector<int64_t> ldx(count);
+  std::vector<Plan> plans(count);
+  mi_status s = MI_OK;
+  for (int64_t d = 0; d < count; ++d) {
+    s = check_problem(&probs[d], &ldx[d]);
+    if (s != MI_OK) {
+      const std::string why = last_error();
+      return fail(s, "problem %lld: %s", (long long)d, why.c_str());
+    }
+    if (probs[d].validate) return fail(MI_ERR_INVALID_ARG, "problem %lld: validate is not supported in batches", (long long)d);
+  }
+  DeviceInfo di;
+  s = device_info(&di);
+  if (s != MI_OK) return s;
+
+  if (mode == MI_BATCH_PERSISTENT) {
+    // Split each dataset's K range so that no unit is much larger than the
+    // average share of one persistent slot: units of very different datasets
+    // then balance in the dynamic queue.
+    double total = 0.0;
+    for (int64_t d = 0; d < count; ++d) {
+      if (probs[d].n == 0) continue;
+      Plan p0;
+      s = choose_plan(probs[d].m, probs[d].n, is_aligned(probs[d].X, ldx[d]), probs[d].tile, 1, &p0);
+      if (s != MI_OK) return s;
+      total += (double)p0.ntiles * p0.bt * p0.bt * (double)probs[d].m;
+      plans[d] = p0;
+    }
+    const double slots = (double)di.cus * di.pocc[0];
+    const double target = std::max(total / (slots * 4.0), 1.0);
+    for (int64_t d = 0; d < count; ++d) {
+      if (probs[d].n == 0) continue;
+      int sp = probs[d].splits;
+      if (sp <= 0) {
+        const double unit = (double)plans[d].bt * plans[d].bt * (double)probs[d].m;
+        sp = (int)std::min<double>(std::ceil(unit / target), std::max<int64_t>(1, probs[d].m / 1024));
+        sp = std::max(sp, 1);
+      }
+      plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].bt, sp);
+    }
+  } else {
+    for (int64_t d = 0; d < count; ++d) {
+      if (probs[d].n == 0) continue;
+      s = choose_plan(probs[d].m, probs[d].n, is_aligned(probs[d].X, ldx[d]), probs[d].tile, probs[d].splits, &plans[d]);
+      if (s != MI_OK) return s;
+    }
+  }
+
+  // One workspace holding every dataset's split region.
+  std::vector<size_t> ws_off(count, 0);
+  size_t ws_total = 0;
+  for (int64_t d = 0; d < count; ++d) {
+    if (probs[d].n == 0) continue;
+    ws_off[d] = ws_total;
+    ws_total += (workspace_bytes(plans[d]) + 255) & ~(size_t)255;
+  }
+  void* ws = nullptr;
+  s = workspace(st, 1, ws_total, &ws);
+  if (s != MI_OK) return s;
+  std::vector<ProbDev> P(count);
+  for (int64_t d = 0; d < count; ++d) {
+    if (probs[d].n == 0) continue;
+    P[d] = make_probdev(&probs[d], ldx[d], plans[d], ws ? (char*)ws + ws_off[d] : nullptr);
+  }
+
+  if (mode == MI_BATCH_SEQUENTIAL) {
+    for (int64_t d = 0; d < count; ++d)
+      if (probs[d].n > 0) HIPCHK(launch_plain(plans[d].bt, P[d], st));
+    return MI_OK;
+  }
+
+  if (mode == MI_BATCH_GRAPH) {
+    const std::string key = batch_key(probs, count, plans, st);
+    hipGraphExec_t exec = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      auto it = g_graphs.find(key);
+      if (it != g_graphs.end()) exec = it->second.exec;
+    }
+    if (!exec) {
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int64_t d = 0; d < count; ++d) {
+        if (probs[d].n == 0) continue;
+        hipError_t e = launch_plain(plans[d].bt, P[d], st);
+        if (e != hipSuccess) {
+          hipGraph_t g2 = nullptr;
+          (void)hipStreamEndCapture(st, &g2);
+          if (g2) (void)hipGraphDestroy(g2);
+          return fail(MI_ERR_DEVICE, "capture launch %lld: %s", (long long)d, hipGetErrorString(e));
+        }
+      }
+      HIPCHK(hipStreamEndCapture(st, &graph));
+      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail(MI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      if (g_graphs.size() > 64) {
+        for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second.exec);
+        g_graphs.clear();
+      }
+      g_graphs[key].exec = exec;
+    }
+    HIPCHK(hipGraphLaunch(exec, st));
+    return MI_OK;
+  }
+
+  // Persistent: work list sorted by decreasing unit cost, one launch per tile size.
+  std::vector<UnitRef> units[2];
+  for (int64_t d = 0; d < count; ++d) {
+    if (probs[d].n == 0) continue;
+    const int b = plans[d].bt == 256 ? 1 : 0;
+    for (int sp = 0; sp < plans[d].splits; ++sp)
+      for (int t = 0; t < plans[d].ntiles; ++t) units[b].push_back(UnitRef{(int32_t)d, t, sp, 0});
+  }
+  for (int b = 0; b < 2; ++b) {
+    std::stable_sort(units[b].begin(), units[b].end(), [&](const UnitRef& x, const UnitRef& y) {
+      const int64_t rx = std::min<int64_t>(P[x.prob].kchunk, P[x.prob].m - (int64_t)x.split * P[x.prob].kchunk);
+      const int64_t ry = std::min<int64_t>(P[y.prob].kchunk, P[y.prob].m - (int64_t)y.split * P[y.prob].kchunk);
+      return rx > ry;
+    });
+  }
+  const size_t probs_bytes = ((sizeof(ProbDev) * count) + 255) & ~(size_t)255;
+  const size_t units_bytes = ((sizeof(UnitRef) * (units[0].size() + units[1].size())) + 255) & ~(size_t)255;
+  const size_t total = probs_bytes + units_bytes + 256;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchBufs& bb = g_batch[{dev, st}];
+  if (bb.copied) HIPCHK(hipEventSynchronize(bb.copied));  // staging buffer free again
+  if (bb.host_bytes < total) {
+    if (bb.host) HIPCHK(hipHostFree(bb.host));
+    bb.host = nullptr;
+    HIPCHK(hipHostMalloc(&bb.host, total, hipHostMallocDefault));
+    bb.host_bytes = total;
+  }
+  if (bb.dev_bytes < total) {
+    if (bb.dev) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipFree(bb.dev));
+    }
+    bb.dev = nullptr;
+    if (hipMalloc(&bb.dev, total) != hipSuccess) {
+      (void)hipGetLastError();
+      bb.dev_bytes = 0;
+      return fail(MI_ERR_OUT_OF_MEMORY, "batch descriptor allocation failed");
+    }
+    bb.dev_bytes = total;
+  }
+  if (!bb.copied) HIPCHK(hipEventCreateWithFlags(&bb.copied, hipEventDisableTiming));
+  char* h = (char*)bb.host;
+  std::memcpy(h, P.data(), sizeof(ProbDev) * count);
+  std::memcpy(h + probs_bytes, units[0].data(), sizeof(UnitRef) * units[0].size());
+  std::memcpy(h + probs_bytes + sizeof(UnitRef) * units[0].size(), units[1].data(), sizeof(UnitRef) * units[1].size());
+  HIPCHK(hipMemcpyAsync(bb.dev, bb.host, probs_bytes + units_bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(bb.copied, st));
+  char* dv = (char*)bb.dev;
+  const ProbDev* dP = (const ProbDev*)dv;
+  const UnitRef* dU = (const UnitRef*)(dv + probs_bytes);
+  int* head = (int*)(dv + probs_bytes + units_bytes);
+  const int grid0 = di.cus * di.pocc[0];
+  const int grid1 = di.cus * di.pocc[1];
+  HIPCHK(launch_persistent(128, dP, dU, (int)units[0].size(), head, std::min<int64_t>(grid0, units[0].size()), st));
+  HIPCHK(launch_persistent(256, dP, dU + units[0].size(), (int)units[1].size(), head + 1,
+                           std::min<int64_t>(grid1, units[1].size()), st));
+  return MI_OK;
+}
+
+// ------------------------------------------------------------------- tuner --
+mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms) {
+  if (m <= 0 || m > INT32_MAX || n <= 0 || n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "bad shape for tuning");
+  if (ldx == 0) ldx = n;
+  if (ldx < n) return fail(MI_ERR_INVALID_ARG, "ldx < n");
+  DeviceInfo di;
+  mi_status s = device_info(&di);
+  if (s != MI_OK) return s;
+  uint8_t* X = nullptr;
+  float* out = nullptr;
+  const size_t xbytes = (size_t)m * (size_t)ldx;
+  if (hipMalloc(&X, xbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MI_ERR_OUT_OF_MEMORY, "tuner: X allocation failed");
+  }
+  if (hipMalloc(&out, (size_t)n * n * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(X);
+    return fail(MI_ERR_OUT_OF_MEMORY, "tuner: out allocation failed");
+  }
+  HIPCHK(hipMemset(X, 0, xbytes));
+  hipStream_t st = nullptr;
+  HIPCHK(hipStreamCreate(&st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool aligned = is_aligned(X, ldx);
+  Tuned best{0, 0, 1e30};
+  const int bts[2] = {128, 256};
+  for (int bt : bts) {
+    const Plan p1 = make_plan(m, n, bt, 1);
+    const int slots = di.cus * di.occ[bt == 256 ? 1 : 0];
+    std::vector<int> cands;
+    const int64_t steps = cdiv(m, KT);
+    for (int sp : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256}) {
+      if (sp > steps) break;
+      cands.push_back(sp);
+    }
+    cands.push_back(heuristic_splits(m, p1.ntiles, slots));
+    std::sort(cands.begin(), cands.end());
+    cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+    for (int sp : cands) {
+      const Plan pl = make_plan(m, n, bt, sp);
+      if ((double)pl.ntiles * pl.splits > 4.0e6) continue;
+      void* ws = nullptr;
+      s = workspace(st, 0, workspace_bytes(pl), &ws);
+      if (s != MI_OK) break;
+      mi_problem pr;
+      mi_problem_init(&pr, X, m, n, out);
+      pr.ldx = ldx;
+      const ProbDev P = make_probdev(&pr, ldx, pl, ws);
+      HIPCHK(launch_plain(bt, P, st));  // warm-up
+      float best_here = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(hipEventRecord(e0, st));
+        HIPCHK(launch_plain(bt, P, st));
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        best_here = std::min(best_here, ms);
+      }
+      if (best_here < best.ms) best = Tuned{bt, pl.splits, best_here};
+    }
+    if (s != MI_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  {
+    // the tuner's workspace was keyed on its private stream: release it
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find(WsKey{dev, st, 0});
+    if (it != g_ws.end()) {
+      (void)hipFree(it->second.ptr);
+      g_ws.erase(it);
+    }
+  }
+  (void)hipStreamDestroy(st);
+  (void)hipFree(X);
+  (void)hipFree(out);
+  if (s != MI_OK) return s;
+  if (best.bt == 0) return fail(MI_ERR_DEVICE, "tuner found no runnable configuration");
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[shape_key(m, n, aligned)] = best;
+  }
+  if (tile) *tile = best.bt == 256 ? MI_TILE_256 : MI_TILE_128;
+  if (splits) *splits = best.splits;
+  if (best_ms) *best_ms = best.ms;
+  return MI_OK;
+}
+
+mi_status tuner_save(const char* path) {
+  if (!path) return fail(MI_ERR_INVALID_ARG, "path is NULL");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(MI_ERR_INVALID_ARG, "cannot open %s for writing", path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : g_tuned)
+    fprintf(f, "{\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %.6f}\n", kv.first.mb,
+            kv.first.nb, kv.first.aligned, kv.second.bt, kv.second.splits, kv.second.ms);
+  fclose(f);
+  return MI_OK;
+}
+
+mi_status tuner_load(const char* path) {
+  if (!path) return fail(MI_ERR_INVALID_ARG, "path is NULL");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(MI_ERR_INVALID_ARG, "cannot open %s", path);
+  char line[512];
+  int nread = 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  while (fgets(line, sizeof line, f)) {
+    ShapeKey k;
+    Tuned t;
+    if (sscanf(line, " {\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %lf}", &k.mb,
+               &k.nb, &k.aligned, &t.bt, &t.splits, &t.ms) == 6 &&
+        (t.bt == 128 || t.bt == 256) && t.splits >= 1) {
+      g_tuned[k] = t;
+      ++nread;
+    }
+  }
+  fclose(f);
+  (void)nread;
+  return MI_OK;
+}
+
+void tuner_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
+}
+
+}  // namespace mi
+
+// ===================================================================== C ABI
+using namespace mi;
+
+extern "C" {
+
+void mi_problem_init(mi_problem* p, const uint8_t* X, int64_t m, int64_t n, float* out) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->X = X;
+  p->m = m;
+  p->n = n;
+  p->ldx = n;
+  p->out = out;
+  p->epilogue = MI_EPI_FP32;
+  p->fallback_tau = 1e-3f;
+}
+
+mi_status mi_all_pairs_ex(const mi_problem* p, void* stream) {
+  clear_error();
+  return run_one(p, (hipStream_t)stream, 0);
+}
+
+mi_status mi_all_pairs_async(const uint8_t* X, int64_t m, int64_t n, float* out, void* stream) {
+  mi_problem p;
+  mi_problem_init(&p, X, m, n, out);
+  return mi_all_pairs_ex(&p, stream);
+}
+
+mi_status mi_all_pairs(const uint8_t* X, int64_t m, int64_t n, float* out) {
+  mi_status s = mi_all_pairs_async(X, m, n, out, nullptr);
+  if (s != MI_OK) return s;
+  hipError_t e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return fail(MI_ERR_DEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  return MI_OK;
+}
+
+mi_status mi_all_pairs_batched(const mi_problem* probs, int64_t count, void* stream, int32_t mode) {
+  clear_error();
+  return run_batched(probs, count, (hipStream_t)stream, mode);
+}
+
+mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits) {
+  clear_error();
+  if (m <= 0 || m > INT32_MAX || n < 0 || n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "bad shape");
+  if (ldx == 0) ldx = n;
+  if (ldx < n) return fail(MI_ERR_INVALID_ARG, "ldx < n");
+  Plan pl;
+  mi_status s = choose_plan(m, std::max<int64_t>(n, 1), ldx % 16 == 0, 0, 0, &pl);
+  if (s != MI_OK) return s;
+  if (tile) *tile = pl.bt == 256 ? MI_TILE_256 : MI_TILE_128;
+  if (splits) *splits = pl.splits;
+  return MI_OK;
+}
+
+mi_status mi_tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms) {
+  clear_error();
+  return tune(m, n, ldx, tile, splits, best_ms);
+}
+
+mi_status mi_tuner_save(const char* path) {
+  clear_error();
+  return tuner_save(path);
+}
+
+mi_status mi_tuner_load(const char* path) {
+  clear_error();
+  return tuner_load(path);
+}
+
+void mi_tuner_clear(void) { tuner_clear(); }
+
+const char* mi_last_error(void) { return last_error(); }
+
+const char* mi_version(void) { return "mi355x-binary-mi 0.1 (gfx950, int8 MFMA)"; }
+
+}  // extern "C"

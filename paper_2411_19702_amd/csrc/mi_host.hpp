@@ -1,0 +1,48 @@
+// mi_host.hpp -- host-runtime helpers shared by the C ABI and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mi.h"
+#include "mi_internal.hpp"
+
+namespace mi {
+
+mi_status fail(mi_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+const char* last_error();
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return ::mi::fail(MI_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct DeviceInfo {
+  int device = 0;
+  int cus = 0;
+  int occ[2] = {1, 1};   // plain kernel workgroups per CU, tile 128 / 256
+  int pocc[2] = {1, 1};  // persistent kernel workgroups per CU
+};
+
+struct Plan {
+  int bt = 128;
+  int ntp = 0;
+  int ntiles = 0;
+  int splits = 1;
+  int kchunk = 0;
+};
+
+mi_status device_info(DeviceInfo* out);
+mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out);
+size_t workspace_bytes(const Plan& pl);
+Plan make_plan(int64_t m, int64_t n, int bt, int splits);
+mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out);
+mi_status check_problem(const mi_problem* p, int64_t* ldx_out);
+bool is_aligned(const uint8_t* X, int64_t ldx);
+ProbDev make_probdev(const mi_problem* p, int64_t ldx, const Plan& pl, void* ws);
+mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot);
+mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode);
+
+}  // namespace mi

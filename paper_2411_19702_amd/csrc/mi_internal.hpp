@@ -1,0 +1,27 @@
+// mi_internal.hpp -- declarations shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mi_device.hpp"
+
+namespace mi {
+
+// One entry of the persistent kernel's work list.
+struct UnitRef {
+  int32_t prob;
+  int32_t tile;
+  int32_t split;
+  int32_t pad;
+};
+
+hipError_t launch_plain(int bt, const ProbDev& P, hipStream_t st);
+hipError_t launch_persistent(int bt, const ProbDev* probs, const UnitRef* units, int nunits, int* head, int grid,
+                             hipStream_t st);
+hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st);
+hipError_t fill_i32(int* p, int v, int count, hipStream_t st);
+int occupancy(int bt);
+int persistent_occupancy(int bt);
+
+}  // namespace mi

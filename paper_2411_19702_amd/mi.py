@@ -1,0 +1,210 @@
+"""Python binding of libmi.so (include/mi.h), with the same entry-point names.
+
+Argument marshalling only: tensors are passed by device pointer and the
+current torch stream by handle; every step of the computation runs in the HIP
+library.  There is no fallback -- if the library is not built, or a tensor is
+not on the GPU, the call raises.
+
+X is a 2-D uint8 (or int8/bool) tensor on the GPU of shape (m, n) whose rows
+may be padded: X.stride(1) must be 1 and X.stride(0) is the row pitch ldx.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmi.so")
+
+MI_OK = 0
+STATUS_NAMES = {
+    0: "MI_OK", 1: "MI_ERR_INVALID_ARG", 2: "MI_ERR_NOT_BINARY", 3: "MI_ERR_OUT_OF_MEMORY", 4: "MI_ERR_BUDGET",
+    5: "MI_ERR_QUEUE_FULL", 6: "MI_ERR_NOT_READY", 7: "MI_ERR_DEVICE", 8: "MI_ERR_TIMEOUT", 9: "MI_ERR_UNKNOWN_TICKET",
+}
+MI_EPI_FP32, MI_EPI_FP32_FP64_FALLBACK, MI_EPI_FP64 = 0, 1, 2
+MI_TILE_AUTO, MI_TILE_128, MI_TILE_256 = 0, 1, 2
+MI_BATCH_PERSISTENT, MI_BATCH_GRAPH, MI_BATCH_SEQUENTIAL = 0, 1, 2
+
+
+class MIError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class mi_problem(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("ldx", ctypes.c_int64),
+        ("out", ctypes.c_void_p),
+        ("n11_out", ctypes.c_void_p),
+        ("colsum_out", ctypes.c_void_p),
+        ("epilogue", ctypes.c_int32),
+        ("fallback_tau", ctypes.c_float),
+        ("validate", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("splits", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_float
+    P = ctypes.POINTER
+    sig = {
+        "mi_problem_init": (None, [P(mi_problem), vp, i64, i64, vp]),
+        "mi_all_pairs": (i32, [vp, i64, i64, vp]),
+        "mi_all_pairs_async": (i32, [vp, i64, i64, vp, vp]),
+        "mi_all_pairs_ex": (i32, [P(mi_problem), vp]),
+        "mi_all_pairs_batched": (i32, [P(mi_problem), i64, vp, i32]),
+        "mi_plan": (i32, [i64, i64, i64, P(i32), P(i32)]),
+        "mi_tune": (i32, [i64, i64, i64, P(i32), P(i32), P(ctypes.c_double)]),
+        "mi_tuner_save": (i32, [ctypes.c_char_p]),
+        "mi_tuner_load": (i32, [ctypes.c_char_p]),
+        "mi_tuner_clear": (None, []),
+        "mi_last_error": (ctypes.c_char_p, []),
+        "mi_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != MI_OK:
+        msg = lib().mi_last_error()
+        raise MIError(status, msg.decode() if msg else "")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _x_layout(X: torch.Tensor, n: Optional[int]) -> Tuple[int, int, int]:
+    if not isinstance(X, torch.Tensor) or X.dim() != 2:
+        raise ValueError("X must be a 2-D tensor (rows x columns)")
+    if not X.is_cuda:
+        raise ValueError("X must be on the GPU (the library has no CPU path)")
+    if X.dtype not in (torch.uint8, torch.int8, torch.bool):
+        raise ValueError("X must hold bytes (uint8/int8/bool) with values 0/1")
+    m, cols = X.shape
+    if m > 1 and X.stride(1) != 1:
+        raise ValueError("X rows must be contiguous (stride(1) == 1)")
+    ldx = X.stride(0) if m > 1 else max(cols, 1)
+    n = cols if n is None else n
+    if n > cols:
+        raise ValueError("n exceeds X.shape[1]")
+    return m, n, ldx
+
+
+def make_problem(X: torch.Tensor, out: torch.Tensor, n: Optional[int] = None, n11_out: Optional[torch.Tensor] = None,
+                 colsum_out: Optional[torch.Tensor] = None, epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3,
+                 validate: bool = False, tile: int = 0, splits: int = 0) -> mi_problem:
+    m, n, ldx = _x_layout(X, n)
+    for name, t, dt in (("out", out, torch.float32), ("n11_out", n11_out, torch.int32), ("colsum_out", colsum_out, torch.int32)):
+        if t is None:
+            continue
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} GPU tensor")
+    if out.numel() < n * n or (n11_out is not None and n11_out.numel() < n * n) or (colsum_out is not None and colsum_out.numel() < n):
+        raise ValueError("output tensor too small")
+    p = mi_problem()
+    p.X, p.m, p.n, p.ldx = X.data_ptr(), m, n, ldx
+    p.out, p.n11_out, p.colsum_out = out.data_ptr(), _ptr(n11_out), _ptr(colsum_out)
+    p.epilogue, p.fallback_tau, p.validate = int(epilogue), float(fallback_tau), 1 if validate else 0
+    p.tile, p.splits = int(tile), int(splits)
+    return p
+
+
+def _new_out(X: torch.Tensor, n: Optional[int]) -> torch.Tensor:
+    n = X.shape[1] if n is None else n
+    return torch.empty((n, n), dtype=torch.float32, device=X.device)
+
+
+def mi_all_pairs(X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Blocking MI matrix of X (contiguous m x n) on the default stream."""
+    m, n, ldx = _x_layout(X, None)
+    if ldx != n:
+        raise ValueError("mi_all_pairs needs a dense X; use mi_all_pairs_ex for a pitched X")
+    out = _new_out(X, n) if out is None else out
+    _check(lib().mi_all_pairs(X.data_ptr(), m, n, out.data_ptr()))
+    return out
+
+
+def mi_all_pairs_async(X: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    m, n, ldx = _x_layout(X, None)
+    if ldx != n:
+        raise ValueError("mi_all_pairs_async needs a dense X; use mi_all_pairs_ex for a pitched X")
+    out = _new_out(X, n) if out is None else out
+    _check(lib().mi_all_pairs_async(X.data_ptr(), m, n, out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def mi_all_pairs_ex(X: torch.Tensor, out: Optional[torch.Tensor] = None, n: Optional[int] = None, stream=None,
+                    **kw) -> torch.Tensor:
+    out = _new_out(X, n) if out is None else out
+    p = make_problem(X, out, n=n, **kw)
+    _check(lib().mi_all_pairs_ex(ctypes.byref(p), _stream_handle(stream)))
+    return out
+
+
+def mi_all_pairs_batched(problems: Sequence[mi_problem], mode: int = MI_BATCH_PERSISTENT, stream=None) -> None:
+    arr = (mi_problem * len(problems))(*problems)
+    _check(lib().mi_all_pairs_batched(arr, len(problems), _stream_handle(stream), int(mode)))
+
+
+def mi_plan(m: int, n: int, ldx: int = 0) -> Tuple[int, int]:
+    t, s = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mi_plan(m, n, ldx, ctypes.byref(t), ctypes.byref(s)))
+    return t.value, s.value
+
+
+def mi_tune(m: int, n: int, ldx: int = 0) -> Tuple[int, int, float]:
+    t, s, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().mi_tune(m, n, ldx, ctypes.byref(t), ctypes.byref(s), ctypes.byref(ms)))
+    return t.value, s.value, ms.value
+
+
+def mi_tuner_save(path: str) -> None:
+    _check(lib().mi_tuner_save(path.encode()))
+
+
+def mi_tuner_load(path: str) -> None:
+    _check(lib().mi_tuner_load(path.encode()))
+
+
+def mi_tuner_clear() -> None:
+    lib().mi_tuner_clear()
+
+
+def mi_last_error() -> str:
+    return (lib().mi_last_error() or b"").decode()
+
+
+def mi_version() -> str:
+    return lib().mi_version().decode()

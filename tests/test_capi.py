@@ -1,0 +1,124 @@
+"""The C-ABI library on the CPU (no GPU): it builds, loads, exports every
+symbol the headers declare, and its host-side argument checks return the
+documented status codes without touching a device."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2411_19702_amd import build, mi
+    if build.is_stale():
+        build.build_library()
+    return mi.lib()
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(mi_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_headers_declare_the_boundary():
+    names = declared_functions()
+    for required in ("mi_all_pairs", "mi_all_pairs_async", "mi_all_pairs_ex", "mi_all_pairs_batched",
+                     "mi_last_error", "mi_tune"):
+        assert required in names, required
+
+
+def test_library_exports_every_declared_symbol(L):
+    from paper_2411_19702_amd import mi
+    out = subprocess.run(["nm", "-D", "--defined-only", mi.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT\s+(\w+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_library_has_gfx950_code_object():
+    from paper_2411_19702_amd import mi
+    data = open(mi.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def _problem(mi, **kw):
+    p = mi.mi_problem()
+    mi.lib().mi_problem_init(ctypes.byref(p), None, 10, 4, None)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [("m", 0), ("m", -3), ("m", 2 ** 31), ("n", -1), ("ldx", 3), ("epilogue", 3),
+                                         ("epilogue", -1), ("tile", 7), ("splits", -2)])
+def test_invalid_arguments_rejected_on_host(L, field, value):
+    from paper_2411_19702_amd import mi
+    p = _problem(mi, X=16, out=16)
+    setattr(p, field, value)
+    st = L.mi_all_pairs_ex(ctypes.byref(p), None)
+    assert st == 1, (field, value, st)
+    assert L.mi_last_error()
+
+
+def test_null_pointers_rejected_and_empty_is_noop(L):
+    from paper_2411_19702_amd import mi
+    p = _problem(mi)                      # X = out = NULL, n = 4
+    assert L.mi_all_pairs_ex(ctypes.byref(p), None) == 1
+    assert b"NULL" in L.mi_last_error()
+    p.n = 0                               # n == 0 is a no-op even with NULL pointers
+    assert L.mi_all_pairs_ex(ctypes.byref(p), None) == 0
+    assert L.mi_all_pairs_ex(None, None) == 1
+    assert L.mi_all_pairs(None, 0, 5, None) == 1
+
+
+def test_batched_argument_checks(L):
+    from paper_2411_19702_amd import mi
+    assert L.mi_all_pairs_batched(None, 0, None, 0) == 0
+    assert L.mi_all_pairs_batched(None, -1, None, 0) == 1
+    assert L.mi_all_pairs_batched(None, 3, None, 0) == 1
+    arr = (mi.mi_problem * 2)(_problem(mi, X=16, out=16), _problem(mi, X=16, out=16))
+    assert L.mi_all_pairs_batched(arr, 2, None, 9) == 1       # bad mode
+    arr[1].m = 0
+    assert L.mi_all_pairs_batched(arr, 2, None, 0) == 1
+    assert b"problem 1" in L.mi_last_error()
+    arr[1].m = 10
+    arr[1].validate = 1
+    assert L.mi_all_pairs_batched(arr, 2, None, 0) == 1
+
+
+def test_plan_and_tuner_argument_checks(L, tmp_path):
+    i32 = ctypes.c_int32
+    t, s = i32(), i32()
+    assert L.mi_plan(0, 10, 0, ctypes.byref(t), ctypes.byref(s)) == 1
+    assert L.mi_plan(10, 10, 5, ctypes.byref(t), ctypes.byref(s)) == 1
+    assert L.mi_tune(0, 10, 0, None, None, None) == 1
+    assert L.mi_tuner_load(str(tmp_path / "missing.jsonl").encode()) == 1
+    L.mi_tuner_clear()
+    f = tmp_path / "tuned.jsonl"
+    assert L.mi_tuner_save(str(f).encode()) == 0
+    f.write_text('{"mb": 40, "nb": 16, "aligned": 1, "tile": 128, "splits": 7, "ms": 1.5}\nnot json\n')
+    assert L.mi_tuner_load(str(f).encode()) == 0
+    out = tmp_path / "again.jsonl"
+    assert L.mi_tuner_save(str(out).encode()) == 0
+    assert '"splits": 7' in out.read_text()
+    L.mi_tuner_clear()
+
+
+def test_version_string(L):
+    assert b"gfx950" in L.mi_version()
+
+
+def test_python_binding_refuses_cpu_tensors(L):
+    import torch
+    from paper_2411_19702_amd import mi
+    with pytest.raises(ValueError):
+        mi.mi_all_pairs(torch.zeros((4, 3), dtype=torch.uint8))

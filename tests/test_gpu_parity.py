@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Counts (n11, column sums) must be bit-exact; MI within 1e-5 bits absolute of
+the FP64 oracle; the output matrix bitwise symmetric.  Small shapes are
+compared element by element over the whole matrix; the full-size workloads
+(100,000 x 1,024 and 1,000,000 x 4,096) on every pair of a column sample that
+includes tile boundaries and planted structure.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_19702_amd import mi, synth
+from tests.gpu_util import compare_columns, compare_full, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _gen(spec):
+    return synth.generate(spec, device=DEV)
+
+
+@pytest.mark.parametrize("splits", [0, 1, 2, 5])
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_small_workload_full_matrix(splits, epi):
+    spec = synth.spec_small()
+    say(f"[parity] small 1000x200 splits={splits} epi={epi}")
+    X = _gen(spec)
+    out, n11, cs = run_gpu(X, splits=splits, epilogue=epi)
+    err = compare_full(X.cpu().numpy(), spec.n, out, n11, cs)
+    say(f"  max|dMI|={err:.3e}")
+
+
+EDGE_SHAPES = [(1, 1), (1, 5), (2, 1), (3, 2), (63, 17), (64, 16), (65, 129), (130, 128), (200, 300), (1000, 257),
+               (4097, 130), (129, 385)]
+
+
+@pytest.mark.parametrize("m,n", EDGE_SHAPES)
+def test_edge_shapes(m, n):
+    say(f"[parity] edge m={m} n={n}")
+    spec = synth.spec_random(1000 + m * 7 + n, m, n, 0.0, 1.0)
+    X = _gen(spec)
+    for splits in (1, 3):
+        out, n11, cs = run_gpu(X, splits=splits)
+        compare_full(X.cpu().numpy(), n, out, n11, cs)
+
+
+@pytest.mark.parametrize("fill", ["zeros", "ones", "constant_mix"])
+def test_degenerate_matrices(fill):
+    say(f"[parity] degenerate {fill}")
+    m, n = 300, 140
+    if fill == "zeros":
+        X = torch.zeros((m, n), dtype=torch.uint8, device=DEV)
+    elif fill == "ones":
+        X = torch.ones((m, n), dtype=torch.uint8, device=DEV)
+    else:
+        X = _gen(synth.spec_random(77, m, n, 0.1, 0.9))
+        X[:, ::3] = 0
+        X[:, 1::7] = 1
+    out, n11, cs = run_gpu(X, splits=2)
+    compare_full(X.cpu().numpy(), n, out, n11, cs)
+    if fill in ("zeros", "ones"):
+        assert (out == 0.0).all()
+
+
+def test_pitched_and_misaligned_layouts():
+    m, n = 517, 100
+    base = _gen(synth.spec_random(5, m, 160, 0.05, 0.7))
+    Xh_full = base.cpu().numpy()
+    cases = {
+        "pitch128_aligned": base[:, :n],                    # ldx = 160, aligned rows? 160 % 16 == 0
+        "offset1_misaligned": base[:, 1:1 + n],             # base pointer off by one byte
+        "pitch_odd": torch.zeros((m, 101), dtype=torch.uint8, device=DEV),
+    }
+    cases["pitch_odd"][:, :n] = base[:, :n]
+    cases["pitch_odd"][:, n:] = 1                           # garbage beyond n must be ignored
+    for name, X in cases.items():
+        say(f"[parity] layout {name} ldx={X.stride(0)}")
+        out, n11, cs = run_gpu(X, n=n, splits=2)
+        Xh = X.cpu().numpy()
+        compare_full(Xh, n, out, n11, cs)
+    _ = Xh_full
+
+
+def test_tile_256_path():
+    say("[parity] tile 256")
+    spec = synth.spec_random(31, 2000, 600, 0.01, 0.5, planted=20)
+    X = _gen(spec)
+    for splits in (1, 4):
+        out, n11, cs = run_gpu(X, tile=mi.MI_TILE_256, splits=splits)
+        compare_full(X.cpu().numpy(), spec.n, out, n11, cs)
+
+
+def test_exact_independence_fp64_is_zero():
+    say("[parity] product columns")
+    # columns k div s < r1 and k mod s < s1 are exactly independent: MI = 0.0
+    r, s = 40, 25
+    k = np.arange(r * s)
+    cols = [(k // s < r1) for r1 in (1, 7, 13, 39)] + [(k % s < s1) for s1 in (1, 9, 24)]
+    Xh = np.stack(cols, axis=1).astype(np.uint8)
+    X = torch.from_numpy(Xh).to(DEV)
+    out, n11, cs = run_gpu(X, epilogue=2)
+    for i in range(4):
+        for j in range(4, 7):
+            assert out[i, j] == 0.0 and out[j, i] == 0.0, (i, j, out[i, j])
+    compare_full(Xh, Xh.shape[1], out, n11, cs)
+
+
+def test_validate_flags_non_binary():
+    say("[parity] validate")
+    X = torch.zeros((50, 20), dtype=torch.uint8, device=DEV)
+    X[17, 3] = 2
+    with pytest.raises(mi.MIError) as ei:
+        run_gpu(X, validate=True)
+    assert ei.value.status == 2
+    X[17, 3] = 1
+    out, n11, cs = run_gpu(X, validate=True)
+    compare_full(X.cpu().numpy(), 20, out, n11, cs)
+
+
+def test_repeat_runs_bitwise_identical():
+    say("[parity] determinism")
+    spec = synth.spec_random(8, 20000, 300, 0.01, 0.5)
+    X = _gen(spec)
+    a = run_gpu(X, splits=7)
+    b = run_gpu(X, splits=7)
+    c = run_gpu(X, splits=1)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    for u, v in zip(a, c):
+        assert np.array_equal(u, v)
+
+
+def test_blocking_and_async_entry_points():
+    say("[parity] mi_all_pairs / mi_all_pairs_async")
+    spec = synth.spec_random(9, 999, 77, 0.05, 0.5)
+    X = _gen(spec)
+    a = mi.mi_all_pairs(X)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = mi.mi_all_pairs_async(X, stream=s)
+    s.synchronize()
+    assert torch.equal(a, b)
+    o_n11, o_mi = oracle.all_pairs(X.cpu().numpy())
+    assert np.max(np.abs(a.cpu().numpy() - o_mi)) <= 1e-5
+
+
+def _sample_columns(spec, n_random: int, seed: int, extra=()):
+    rng = np.random.default_rng(seed)
+    n = spec.n
+    cols = {0, 1, n - 1, n - 2}
+    for b in range(128, n, 128):                            # both sides of every 128-column boundary
+        cols.update({b - 1, b})
+    for dst, src, _q in spec.planted[:6]:
+        cols.update({dst, src})
+    for dst, a, b, _op in spec.derived[:4]:
+        cols.update({dst, a, b})
+    cols.update(int(c) for c in rng.choice(n, size=n_random, replace=False))
+    cols.update(extra)
+    return sorted(cols)
+
+
+@pytest.mark.parametrize("epi", [0, 1])
+def test_mid_workload_sampled(epi):
+    spec = synth.spec_mid()
+    say(f"[parity] mid 100000x1024 epi={epi}")
+    X = _gen(spec)
+    out, n11, cs = run_gpu(X, epilogue=epi)
+    cols = _sample_columns(spec, 24, 1)
+    Xs = synth.columns(spec, cols).numpy()
+    err = compare_columns(Xs, cols, out, n11, cs)
+    say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
+
+
+def test_large_workload_sampled():
+    spec = synth.spec_large()
+    say("[parity] large 1000000x4096")
+    X = _gen(spec)
+    out, n11, cs = run_gpu(X)
+    del X
+    torch.cuda.empty_cache()
+    cols = _sample_columns(spec, 8, 2)
+    Xs = synth.columns(spec, cols).numpy()
+    err = compare_columns(Xs, cols, out, n11, cs)
+    say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
