@@ -75,28 +75,32 @@ __device__ __forceinline__ double cell64(int nxy, int nx, int ny, int m) {
   return (double)nxy * log2(num / den);
 }
 
+__device__ __forceinline__ float mi_value64(int m, int ci, int cj, int n11) {
+#pragma clang fp contract(off)
+  const int n10 = ci - n11, n01 = cj - n11, ni0 = m - ci, nj0 = m - cj, n00 = ni0 - n01;
+  const double d11 = cell64(n11, ci, cj, m);
+  const double d00 = cell64(n00, ni0, nj0, m);
+  const double d10 = cell64(n10, ci, nj0, m);
+  const double d01 = cell64(n01, ni0, cj, m);
+  return (float)(((d11 + d00) + (d10 + d01)) / (double)m);
+}
+
 __device__ __forceinline__ float mi_value(int m, int ci, int cj, int n11, int epi, float tau) {
 #pragma clang fp contract(off)
+  if (epi == 2) return mi_value64(m, ci, cj, n11);
   const int n10 = ci - n11;          // X_i = 1, X_j = 0
   const int n01 = cj - n11;          // X_i = 0, X_j = 1
   const int ni0 = m - ci;            // marginal count of X_i = 0
   const int nj0 = m - cj;            // marginal count of X_j = 0
   const int n00 = ni0 - n01;         // = m - c_i - c_j + n11, without overflow
-  float v = 0.0f;
-  if (epi != 2) {
-    const float fm = (float)m;
-    float t11 = cell32(n11, ci, cj, fm);
-    float t00 = cell32(n00, ni0, nj0, fm);
-    float t10 = cell32(n10, ci, nj0, fm);
-    float t01 = cell32(n01, ni0, cj, fm);
-    v = ((t11 + t00) + (t10 + t01)) / fm;
-    if (epi == 0 || !(v < tau)) return v;
-  }
-  double d11 = cell64(n11, ci, cj, m);
-  double d00 = cell64(n00, ni0, nj0, m);
-  double d10 = cell64(n10, ci, nj0, m);
-  double d01 = cell64(n01, ni0, cj, m);
-  return (float)(((d11 + d00) + (d10 + d01)) / (double)m);
+  const float fm = (float)m;
+  const float t11 = cell32(n11, ci, cj, fm);
+  const float t00 = cell32(n00, ni0, nj0, fm);
+  const float t10 = cell32(n10, ci, nj0, fm);
+  const float t01 = cell32(n01, ni0, cj, fm);
+  const float v = ((t11 + t00) + (t10 + t01)) / fm;
+  if (epi == 1 && v < tau) return mi_value64(m, ci, cj, n11);
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -132,46 +136,79 @@ struct Staging {
 };
 
 __device__ __forceinline__ uint32_t keep_mask(int valid, int w) {
-  // bytes of dword w (columns 4w..4w+3 of a 16-byte chunk) that are < valid
-  const int lo = 4 * w;
-  if (valid >= lo + 4) return 0xFFFFFFFFu;
-  if (valid <= lo) return 0u;
-  return (1u << (8 * (valid - lo))) - 1u;
+  // bytes of dword w (columns 4w..4w+3 of a 16-byte chunk) with index < valid
+  const int k = min(max(valid - 4 * w, 0), 4);
+  return (uint32_t)((1ull << (8 * k)) - 1ull);
 }
 
-// Global -> registers for one stage of one panel.
-template <int BT, bool ALIGNED>
-__device__ __forceinline__ void stage_load(uint4 (&r)[Staging<BT>::G][4], const ProbDev& P, int colbase,
-                                           int k0, int kend, int p) {
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+// Per-thread staging context, fixed for a whole unit.
+template <int BT>
+struct StageCtx {
+  int voff[Staging<BT>::G];     // byte offset of the chunk's first row inside a stage
+  int col[Staging<BT>::G];      // first matrix column of the chunk
+  int row[Staging<BT>::G];      // first row of the chunk inside a stage (0..60)
+  uint32_t cm[Staging<BT>::G][4];  // keep-masks for columns >= n
+};
+
+template <int BT>
+__device__ __forceinline__ void stage_ctx(StageCtx<BT>& c, const ProbDev& P, int colbase, int p) {
 #pragma unroll
   for (int gi = 0; gi < Staging<BT>::G; ++gi) {
     const int q = p + gi * HALF;
-    const int col = colbase + Staging<BT>::chunk_col(q);
-    const int row0 = k0 + Staging<BT>::chunk_row(q);
-    const int valid = P.n - col;  // columns of this chunk inside the matrix
+    c.col[gi] = colbase + Staging<BT>::chunk_col(q);
+    c.row[gi] = Staging<BT>::chunk_row(q);
+    const int valid = min(P.n - c.col[gi], 16);
+    // A chunk entirely right of column n reads at an offset past every stage's
+    // buffer range, which the hardware returns as zeros.
+    c.voff[gi] = valid > 0 ? c.row[gi] * (int)P.ldx + c.col[gi] : KT * (int)P.ldx;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int row = row0 + rr;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (row < kend && valid > 0) {
-        const uint8_t* src = P.X + (int64_t)row * P.ldx + col;
-        if (ALIGNED) {
-          v = *reinterpret_cast<const uint4*>(src);
-        } else {
-          uint32_t w[4] = {0u, 0u, 0u, 0u};
+    for (int w = 0; w < 4; ++w) c.cm[gi][w] = keep_mask(valid, w);
+  }
+}
+
+// Global -> registers for the stage starting at row ks (rows >= kend read as 0).
+// Aligned layout: raw buffer loads whose range ends at row min(kend, ks + KT),
+// so out-of-range rows come back as zeros without any branch; the loads of a
+// stage issue back to back and only the consumer waits for them.
+template <int BT, bool ALIGNED>
+__device__ __forceinline__ void stage_load(uint4 (&r)[Staging<BT>::G][4], const ProbDev& P, const StageCtx<BT>& c,
+                                           int ks, int kend) {
+  if (ALIGNED) {
+    // ks and kend are uniform across the workgroup; readfirstlane keeps the
+    // descriptor in scalar registers (no per-lane waterfall around the loads).
+    const int rows = __builtin_amdgcn_readfirstlane(max(0, min(kend - ks, KT)));
+    const int ld = __builtin_amdgcn_readfirstlane((int)P.ldx);
+    const uint64_t base = (uint64_t)(P.X + (int64_t)min(ks, P.m - 1) * P.ldx);
+    const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+    const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+    __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(((uint64_t)bhi << 32) | blo), 0, rows * ld, 0x00020000);
+#pragma unroll
+    for (int gi = 0; gi < Staging<BT>::G; ++gi)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        // the whole offset goes in the vector operand, which the range check covers
+        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, c.voff[gi] + rr * ld, 0, 0);
+        r[gi][rr] = make_uint4(v.x, v.y, v.z, v.w);
+      }
+  } else {
+#pragma unroll
+    for (int gi = 0; gi < Staging<BT>::G; ++gi) {
+      const int valid = min(P.n - c.col[gi], 16);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = ks + c.row[gi] + rr;
+        uint32_t w4[4] = {0u, 0u, 0u, 0u};
+        if (row < kend && valid > 0) {
+          const uint8_t* src = P.X + (int64_t)row * P.ldx + c.col[gi];
 #pragma unroll
           for (int b = 0; b < 16; ++b)
-            if (b < valid) w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
-          v = make_uint4(w[0], w[1], w[2], w[3]);
+            if (b < valid) w4[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
         }
-        if (valid < 16) {
-          v.x &= keep_mask(valid, 0);
-          v.y &= keep_mask(valid, 1);
-          v.z &= keep_mask(valid, 2);
-          v.w &= keep_mask(valid, 3);
-        }
+        r[gi][rr] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
       }
-      r[gi][rr] = v;
     }
   }
 }
@@ -180,25 +217,26 @@ __device__ __forceinline__ uint32_t u4get(const uint4& v, int w) {
   return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
 }
 
-// Registers -> LDS for one stage of one panel: 4x4 byte transposes so that a
-// dword holds 4 consecutive samples of one column, plus column-sum updates.
+// Registers -> LDS for one stage of one panel: mask columns >= n, 4x4 byte
+// transposes so that a dword holds 4 consecutive samples of one column, and
+// column-sum updates.
 template <int BT>
-__device__ __forceinline__ void stage_store(uint8_t* sbuf, const uint4 (&r)[Staging<BT>::G][4],
-                                            uint32_t (&csum)[Staging<BT>::G][16], int p) {
+__device__ __forceinline__ void stage_store(uint8_t* sbuf, const uint4 (&r)[Staging<BT>::G][4], const StageCtx<BT>& c,
+                                            uint32_t (&csum)[Staging<BT>::G][16]) {
 #pragma unroll
   for (int gi = 0; gi < Staging<BT>::G; ++gi) {
-    const int q = p + gi * HALF;
-    const int c0 = Staging<BT>::chunk_col(q);
-    const int rq = Staging<BT>::chunk_row(q) >> 2;  // row quad 0..15
+    const int c0 = c.col[gi] & (BT - 1);          // column inside the panel
+    const int rq = c.row[gi] >> 2;                // row quad 0..15
     const int g = rq >> 2, d = rq & 3;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      const uint32_t a = u4get(r[gi][0], w), b = u4get(r[gi][1], w);
-      const uint32_t c = u4get(r[gi][2], w), e = u4get(r[gi][3], w);
+      const uint32_t m = c.cm[gi][w];
+      const uint32_t a = u4get(r[gi][0], w) & m, b = u4get(r[gi][1], w) & m;
+      const uint32_t cc = u4get(r[gi][2], w) & m, e = u4get(r[gi][3], w) & m;
       const uint32_t x0 = __builtin_amdgcn_perm(b, a, 0x05010400u);  // a0 b0 a1 b1
       const uint32_t x1 = __builtin_amdgcn_perm(b, a, 0x07030602u);  // a2 b2 a3 b3
-      const uint32_t y0 = __builtin_amdgcn_perm(e, c, 0x05010400u);  // c0 e0 c1 e1
-      const uint32_t y1 = __builtin_amdgcn_perm(e, c, 0x07030602u);  // c2 e2 c3 e3
+      const uint32_t y0 = __builtin_amdgcn_perm(e, cc, 0x05010400u); // c0 e0 c1 e1
+      const uint32_t y1 = __builtin_amdgcn_perm(e, cc, 0x07030602u); // c2 e2 c3 e3
       uint32_t o[4];
       o[0] = __builtin_amdgcn_perm(y0, x0, 0x05040100u);  // column 4w+0, rows 0..3
       o[1] = __builtin_amdgcn_perm(y0, x0, 0x07060302u);  // column 4w+1
@@ -223,6 +261,7 @@ struct TileGeom {
   static constexpr int PANEL_BYTES = BT * KT;
   static constexpr int STAGE_BYTES = 2 * PANEL_BYTES;  // panel I then panel J
   static constexpr int LDS_BYTES = 2 * STAGE_BYTES + 2 * BT * 4 + 16;
+  static_assert(4 * 2 * 16 * WT * 4 <= 2 * STAGE_BYTES, "epilogue strips must fit in the stage buffers");
 };
 
 // Decode upper-triangular tile t (row-major over I <= J) into (I, J).
@@ -236,8 +275,9 @@ __device__ __forceinline__ void tile_ij(int t, int ntp, int& I, int& J) {
 
 // One work unit.  smem must hold TileGeom<BT>::LDS_BYTES bytes, 16-aligned.
 template <int BT, bool ALIGNED>
-__device__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
+__device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
   using TG = TileGeom<BT>;
+  using ST = Staging<BT>;
   constexpr int F = TG::F;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -255,12 +295,15 @@ __device__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
   int32_t* sColB = sColA + BT;
   int32_t* sFlag = sColB + BT;
 
-  // Staging role: threads [0, HALF) stage panel I, [HALF, 2 HALF) panel J.
-  // On a diagonal tile both operands come from panel I, the second half idles.
+  // Staging role: threads [0, HALF) stage panel I, [HALF, 2 HALF) panel J (on a
+  // diagonal tile both halves stage the same panel, which keeps the pipeline
+  // free of divergent branches).
   const int half = tid / HALF;
   const int p = tid % HALF;
-  const bool stager = !(diag && half == 1);
   const int colbase = (half == 0 ? I : J) * BT;
+  const int soff = half * TG::PANEL_BYTES;
+  StageCtx<BT> ctx;
+  stage_ctx<BT>(ctx, P, colbase, p);
 
   for (int c = tid; c < 2 * BT; c += NTHREADS) sColA[c] = 0;
 
@@ -270,28 +313,16 @@ __device__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
 #pragma unroll
     for (int b = 0; b < F; ++b) acc[a][b] = v4i{0, 0, 0, 0};
 
-  uint32_t csum[Staging<BT>::G][16];
+  uint32_t csum[ST::G][16];
 #pragma unroll
-  for (int gi = 0; gi < Staging<BT>::G; ++gi)
+  for (int gi = 0; gi < ST::G; ++gi)
 #pragma unroll
     for (int c = 0; c < 16; ++c) csum[gi][c] = 0u;
 
-  uint4 regs[Staging<BT>::G][4];
-  if (nsteps > 0 && stager) {
-    stage_load<BT, ALIGNED>(regs, P, colbase, k0, k1, p);
-    stage_store<BT>(smem + half * TG::PANEL_BYTES, regs, csum, p);
-  }
-  __syncthreads();
-
-  for (int step = 0; step < nsteps; ++step) {
-    uint8_t* cur = smem + (step & 1) * TG::STAGE_BYTES;
-    uint8_t* nxt = smem + ((step + 1) & 1) * TG::STAGE_BYTES;
-    const bool more = (step + 1 < nsteps);
-    if (more && stager) stage_load<BT, ALIGNED>(regs, P, colbase, k0 + (step + 1) * KT, k1, p);
-
+  const int g = lane >> 4;
+  auto mma_stage = [&](const uint8_t* cur) {
     const uint8_t* sA = cur;
-    const uint8_t* sB = diag ? cur : cur + TG::PANEL_BYTES;
-    const int g = lane >> 4;
+    const uint8_t* sB = cur + TG::PANEL_BYTES;
     v4i fa[F], fb[F];
 #pragma unroll
     for (int a = 0; a < F; ++a)
@@ -304,25 +335,44 @@ __device__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
 #pragma unroll
       for (int b = 0; b < F; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  };
 
-    if (more && stager) stage_store<BT>(nxt + half * TG::PANEL_BYTES, regs, csum, p);
+  // Two register sets: during step s the loads of step s + 2 are in flight
+  // while step s + 1 waits in the other set, so each load has two steps of
+  // matrix work to hide behind.  Loads past the unit's rows are zeroed, not
+  // skipped, so the loop body has no data-dependent branches.
+  uint4 r0[ST::G][4], r1[ST::G][4];
+  stage_load<BT, ALIGNED>(r0, P, ctx, k0, k1);
+  stage_load<BT, ALIGNED>(r1, P, ctx, k0 + KT, k1);
+  stage_store<BT>(smem + soff, r0, ctx, csum);
+  __syncthreads();
+
+  // An even number of steps, no exits inside the body: a stage past the
+  // unit's last row loads as zeros and adds nothing to the counts.
+  for (int step = 0; step < nsteps; step += 2) {
+    // even step: compute buffer 0, refill r0 with step + 2, store r1 (step + 1) into buffer 1
+    stage_load<BT, ALIGNED>(r0, P, ctx, k0 + (step + 2) * KT, k1);
+    mma_stage(smem);
+    stage_store<BT>(smem + TG::STAGE_BYTES + soff, r1, ctx, csum);
+    __syncthreads();
+    // odd step: compute buffer 1, refill r1 with step + 3, store r0 (step + 2) into buffer 0
+    stage_load<BT, ALIGNED>(r1, P, ctx, k0 + (step + 3) * KT, k1);
+    mma_stage(smem + TG::STAGE_BYTES);
+    stage_store<BT>(smem + soff, r0, ctx, csum);
     __syncthreads();
   }
 
   // Column sums of this unit's rows: reduce the per-thread partials in LDS.
-  if (stager) {
+  {
     int32_t* dst = (half == 0) ? sColA : sColB;
 #pragma unroll
     for (int gi = 0; gi < Staging<BT>::G; ++gi) {
-      const int c0 = Staging<BT>::chunk_col(p + gi * HALF);
+      const int c0 = ctx.col[gi] & (BT - 1);
 #pragma unroll
       for (int c = 0; c < 16; ++c)
         if (csum[gi][c]) atomicAdd(&dst[c0 + c], (int32_t)csum[gi][c]);
     }
   }
-  __syncthreads();
-  if (diag)
-    for (int c = tid; c < BT; c += NTHREADS) sColB[c] = sColA[c];
   __syncthreads();
 
   // Split-K: publish partials; the last unit of the tile takes over.
@@ -375,7 +425,11 @@ __device__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
     __syncthreads();
   }
 
-  // Epilogue: derived cells, MI, tile and mirror write-back.
+  // Epilogue: derived cells, MI, tile and mirror write-back.  Each wave moves
+  // its accumulators through LDS (the stage buffers are free now) one 16-row
+  // strip at a time: pass 1 reads the strip row-wise, evaluates MI once per
+  // element and writes the tile rows (consecutive lanes, consecutive j); pass 2
+  // reads the strip column-wise and writes the mirror rows (consecutive i).
   const int n = P.n;
   const int64_t ln = n;
   if (diag && P.colsum_out) {
@@ -384,29 +438,43 @@ __device__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
       if (i < n) P.colsum_out[i] = sColA[c];
     }
   }
+  constexpr int WT = TG::WT;
+  constexpr int STRIP = 16 * WT;                       // elements per strip
+  int32_t* sN = reinterpret_cast<int32_t*>(smem) + wave * 2 * STRIP;
+  float* sM = reinterpret_cast<float*>(sN + STRIP);
+  const int ibase = I * BT + wm * WT;
+  const int jbase = J * BT + wn * WT;
 #pragma unroll
   for (int a = 0; a < F; ++a) {
 #pragma unroll
-    for (int b = 0; b < F; ++b) {
-      const int col = wn * TG::WT + b * 16 + (lane & 15);
-      const int j = J * BT + col;
-      const int cj = sColB[col];
+    for (int b = 0; b < F; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = wm * TG::WT + a * 16 + 4 * (lane >> 4) + r;
-        const int i = I * BT + row;
+      for (int r = 0; r < 4; ++r) sN[(4 * (lane >> 4) + r) * WT + b * 16 + (lane & 15)] = acc[a][b][r];
+    __builtin_amdgcn_wave_barrier();
+    const int i0 = ibase + a * 16;
+    for (int e = lane; e < STRIP; e += 64) {
+      const int rr = e / WT, cc = e % WT;
+      const int i = i0 + rr, j = jbase + cc;
+      const int v11 = sN[e];
+      const float v = mi_value(P.m, sColA[i - I * BT], sColB[j - J * BT], v11, P.epi, P.tau);
+      sM[e] = v;
+      if (i < n && j < n) {
+        P.out[i * ln + j] = v;
+        if (P.n11_out) P.n11_out[i * ln + j] = v11;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (!diag) {
+      for (int e = lane; e < STRIP; e += 64) {
+        const int cc = e / 16, rr = e % 16;
+        const int i = i0 + rr, j = jbase + cc;
         if (i < n && j < n) {
-          const int v11 = acc[a][b][r];
-          const float v = mi_value(P.m, sColA[row], cj, v11, P.epi, P.tau);
-          P.out[i * ln + j] = v;
-          if (!diag) P.out[j * ln + i] = v;
-          if (P.n11_out) {
-            P.n11_out[i * ln + j] = v11;
-            if (!diag) P.n11_out[j * ln + i] = v11;
-          }
+          P.out[j * ln + i] = sM[rr * WT + cc];
+          if (P.n11_out) P.n11_out[j * ln + i] = sN[rr * WT + cc];
         }
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
