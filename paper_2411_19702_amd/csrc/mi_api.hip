@@ -47,25 +47,30 @@ mi_status device_info(DeviceInfo* out) {
     DeviceInfo di;
     di.device = dev;
     HIPCHK(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
-    di.occ[0] = occupancy(128);
-    di.occ[1] = occupancy(256);
-    di.pocc[0] = persistent_occupancy(128);
-    di.pocc[1] = persistent_occupancy(256);
+    for (int c = 0; c < kNumCfg; ++c) {
+      di.occ[c] = occupancy(c);
+      di.pocc[c] = persistent_occupancy(c);
+    }
     it = g_info.emplace(dev, di).first;
   }
   *out = it->second;
   return MI_OK;
 }
 
-// --------------------------------------------------------------- workspace --
-// Split-K needs zeroed int32 scratch per tile.  Kernels leave it zeroed again,
-// so a buffer is cleared only when it is (re)allocated.  Buffers are keyed by
-// (device, stream, slot): work on one stream is ordered, so reuse is safe.
+// ----------------------------------------------------------------- scratch --
+// Device scratch keyed by (device, stream, kind, slot).  Work on one stream is
+// ordered, so a buffer can be reused by the next call on the same stream.
+//   kind 0: split-K workspace.  Kernels leave it zeroed again, so it is
+//           cleared only when it is (re)allocated.
+//   kind 1: repacked copies of inputs whose layout the DMA path cannot read.
 struct WsKey {
   int dev;
   hipStream_t st;
+  int kind;
   int slot;
-  bool operator<(const WsKey& o) const { return std::tie(dev, st, slot) < std::tie(o.dev, o.st, o.slot); }
+  bool operator<(const WsKey& o) const {
+    return std::tie(dev, st, kind, slot) < std::tie(o.dev, o.st, o.kind, o.slot);
+  }
 };
 struct WsBuf {
   void* ptr = nullptr;
@@ -74,13 +79,13 @@ struct WsBuf {
 static std::mutex g_ws_mu;
 static std::map<WsKey, WsBuf> g_ws;
 
-mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out) {
+mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out) {
   *out = nullptr;
   if (bytes == 0) return MI_OK;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  WsBuf& w = g_ws[WsKey{dev, st, slot}];
+  WsBuf& w = g_ws[WsKey{dev, st, kind, slot}];
   if (w.bytes < bytes) {
     if (w.ptr) {
       HIPCHK(hipStreamSynchronize(st));
@@ -88,17 +93,70 @@ mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out) {
       w.ptr = nullptr;
       w.bytes = 0;
     }
-    const size_t sz = std::max(bytes, (size_t)1 << 20);
+    const size_t sz = std::max(bytes + bytes / 8, (size_t)1 << 20);
     if (hipMalloc(&w.ptr, sz) != hipSuccess) {
       (void)hipGetLastError();
       w.ptr = nullptr;
-      return fail(MI_ERR_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed", sz);
+      return fail(MI_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes failed", sz);
     }
-    HIPCHK(hipMemset(w.ptr, 0, sz));
+    if (kind == 0) HIPCHK(hipMemset(w.ptr, 0, sz));
     w.bytes = sz;
   }
   *out = w.ptr;
   return MI_OK;
+}
+
+mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out) { return scratch(st, 0, slot, bytes, out); }
+
+static void release_scratch_of(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (auto it = g_ws.begin(); it != g_ws.end();) {
+    if (it->first.st == st) {
+      (void)hipFree(it->second.ptr);
+      it = g_ws.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+int64_t packed_pitch(int64_t n) { return (n + 15) / 16 * 16; }
+
+// --------------------------------------------------------------- tile order --
+// Upper-triangular tiles (I <= J) sorted along a Morton curve of (I, J): a
+// contiguous run of the order is a compact block of the triangle, so the
+// tiles one XCD owns share few column panels.  One table per panel count.
+static std::mutex g_tiles_mu;
+static std::map<std::pair<int, int>, int32_t*> g_tiles;
+
+static uint32_t morton2(uint32_t x, uint32_t y) {
+  uint32_t r = 0;
+  for (int b = 0; b < 16; ++b) r |= ((x >> b) & 1u) << (2 * b + 1) | ((y >> b) & 1u) << (2 * b);
+  return r;
+}
+
+const int32_t* tile_table(int ntp, hipError_t* err) {
+  *err = hipSuccess;
+  int dev = 0;
+  if ((*err = hipGetDevice(&dev)) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  auto it = g_tiles.find({dev, ntp});
+  if (it != g_tiles.end()) return it->second;
+  std::vector<std::pair<uint32_t, int32_t>> order;
+  order.reserve((size_t)ntp * (ntp + 1) / 2);
+  for (int I = 0; I < ntp; ++I)
+    for (int J = I; J < ntp; ++J) order.push_back({morton2((uint32_t)I, (uint32_t)J), (int32_t)((I << 16) | J)});
+  std::sort(order.begin(), order.end());
+  std::vector<int32_t> h(order.size());
+  for (size_t k = 0; k < order.size(); ++k) h[k] = order[k].second;
+  int32_t* d = nullptr;
+  if ((*err = hipMalloc(&d, std::max<size_t>(h.size(), 1) * sizeof(int32_t))) != hipSuccess) return nullptr;
+  if ((*err = hipMemcpy(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  g_tiles[{dev, ntp}] = d;
+  return d;
 }
 
 // ----------------------------------------------------------------- planner --
@@ -110,11 +168,13 @@ size_t workspace_bytes(const Plan& pl) {
   return (size_t)(pl.ntiles * per * sizeof(int32_t) + 256);
 }
 
-Plan make_plan(int64_t m, int64_t n, int bt, int splits) {
+Plan make_plan(int64_t m, int64_t n, int cfg, int splits) {
   Plan pl;
-  pl.bt = bt;
-  pl.ntp = (int)cdiv(n, bt);
+  pl.cfg = cfg;
+  pl.bt = cfg_tile(cfg);
+  pl.ntp = (int)cdiv(std::max<int64_t>(n, 1), pl.bt);
   pl.ntiles = pl.ntp * (pl.ntp + 1) / 2;
+  pl.tpx = (int)cdiv(pl.ntiles, 8);
   const int64_t steps = cdiv(m, KT);
   if (splits < 1) splits = 1;
   if (splits > steps) splits = (int)steps;
@@ -124,31 +184,34 @@ Plan make_plan(int64_t m, int64_t n, int bt, int splits) {
   return pl;
 }
 
-// Heuristic when the tuner has no entry: enough units to fill every slot of
-// the chip in whole waves, with at least kMinRows rows per split so that the
-// workspace flush stays small next to the streamed panels.
-static int heuristic_splits(int64_t m, int ntiles, int slots) {
-  const int64_t kMinRows = 2048;
-  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(256, m / kMinRows));
+// Heuristic when the tuner has no entry: the plain grid is 8 * tpx * splits
+// workgroups (tiles split evenly over the 8 XCDs); pick the number of K splits
+// that fills the chip's slots in whole waves, keeping at least kMinRows rows
+// per split so that the workspace flush stays small next to the streamed rows.
+static int heuristic_splits(int64_t m, const Plan& p1, int slots) {
+  const int64_t kMinRows = 4096;
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(512, m / kMinRows));
   int best = 1;
   double best_eff = 0.0;
   for (int64_t s = 1; s <= smax; ++s) {
-    const double units = (double)ntiles * (double)s;
-    const double waves = std::ceil(units / slots);
-    const double eff = units / (waves * slots);
+    const double busy = (double)p1.ntiles * (double)s;      // units with work
+    const double grid = 8.0 * p1.tpx * (double)s;
+    const double waves = std::ceil(grid / slots);
+    const double eff = busy / (waves * slots);
     if (eff > best_eff + 0.02) {
       best_eff = eff;
       best = (int)s;
     }
-    if (eff > 0.97) break;
+    if (eff > 0.96) break;
   }
   return best;
 }
 
-static int heuristic_tile(int64_t m, int64_t n) {
+// 256-wide tiles halve the panel traffic per MAC; they need enough tiles to
+// occupy the chip, so small matrices use 128-wide tiles.
+static int heuristic_cfg(int64_t m, int64_t n) {
   (void)m;
-  (void)n;
-  return 128;
+  return n >= 1536 ? 1 : 0;
 }
 
 // Tuned entries, keyed by a shape class: m in quarter octaves, n in 64-column
@@ -158,7 +221,7 @@ struct ShapeKey {
   bool operator<(const ShapeKey& o) const { return std::tie(mb, nb, aligned) < std::tie(o.mb, o.nb, o.aligned); }
 };
 struct Tuned {
-  int bt, splits;
+  int cfg, splits;
   double ms;
 };
 static std::mutex g_tune_mu;
@@ -176,26 +239,25 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
   DeviceInfo di;
   mi_status s = device_info(&di);
   if (s != MI_OK) return s;
-  int bt = tile_req == MI_TILE_256 ? 256 : (tile_req == MI_TILE_128 ? 128 : 0);
+  int cfg = tile_req == MI_TILE_256 ? 1 : (tile_req == MI_TILE_128 ? 0 : -1);
   int splits = splits_req;
-  if (bt == 0 || splits <= 0) {
+  if (cfg < 0 || splits <= 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(shape_key(m, n, aligned));
     if (it != g_tuned.end()) {
-      if (bt == 0) bt = it->second.bt;
-      if (splits <= 0 && bt == it->second.bt) splits = it->second.splits;
+      if (cfg < 0) cfg = it->second.cfg;
+      if (splits <= 0 && cfg == it->second.cfg) splits = it->second.splits;
     }
   }
-  if (bt == 0) bt = heuristic_tile(m, n);
-  if (splits <= 0) {
-    const Plan p1 = make_plan(m, n, bt, 1);
-    splits = heuristic_splits(m, p1.ntiles, di.cus * di.occ[bt == 256 ? 1 : 0]);
-  }
-  *out = make_plan(m, n, bt, splits);
+  if (cfg < 0) cfg = heuristic_cfg(m, n);
+  if (splits <= 0) splits = heuristic_splits(m, make_plan(m, n, cfg, 1), di.cus * di.occ[cfg]);
+  *out = make_plan(m, n, cfg, splits);
   return MI_OK;
 }
 
 // -------------------------------------------------------------- arguments --
+// Rows of one 64-row stage are addressed with 32-bit offsets.
+static constexpr int64_t kMaxPitch = (int64_t)1 << 24;
 mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   if (!p) return fail(MI_ERR_INVALID_ARG, "problem is NULL");
   if (p->m <= 0) return fail(MI_ERR_INVALID_ARG, "m must be >= 1 (got %lld)", (long long)p->m);
@@ -204,6 +266,7 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   if (p->n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "n must be <= 2^31-1");
   const int64_t ldx = p->ldx == 0 ? p->n : p->ldx;
   if (ldx < p->n) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)p->n);
+  if (ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) above the supported 2^24", (long long)ldx);
   if (p->n > 0 && (!p->X || !p->out)) return fail(MI_ERR_INVALID_ARG, "X and out must be non-NULL when n > 0");
   if (p->epilogue < 0 || p->epilogue > 2) return fail(MI_ERR_INVALID_ARG, "bad epilogue mode %d", p->epilogue);
   if (p->tile < 0 || p->tile > 2) return fail(MI_ERR_INVALID_ARG, "bad tile id %d", p->tile);
@@ -214,23 +277,25 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
 
 bool is_aligned(const uint8_t* X, int64_t ldx) { return ((uintptr_t)X % 16 == 0) && (ldx % 16 == 0); }
 
-ProbDev make_probdev(const mi_problem* p, int64_t ldx, const Plan& pl, void* ws) {
+ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const Plan& pl, void* ws,
+                     const int32_t* tiles) {
   ProbDev P;
   std::memset(&P, 0, sizeof P);
-  P.X = p->X;
+  P.X = X;
   P.ldx = ldx;
   P.m = (int32_t)p->m;
   P.n = (int32_t)p->n;
   P.out = p->out;
   P.n11_out = p->n11_out;
   P.colsum_out = p->colsum_out;
+  P.tiles = tiles;
   P.ntp = pl.ntp;
   P.ntiles = pl.ntiles;
   P.splits = pl.splits;
   P.kchunk = pl.kchunk;
+  P.tiles_per_xcd = pl.tpx;
   P.epi = p->epilogue;
   P.tau = p->fallback_tau > 0.0f ? p->fallback_tau : 1e-3f;
-  P.aligned = is_aligned(p->X, ldx) ? 1 : 0;
   if (pl.splits > 1 && ws) {
     int32_t* base = reinterpret_cast<int32_t*>(ws);
     P.ws_n11 = base;
@@ -270,14 +335,28 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot) {
     s = validate_binary(p, ldx, st);
     if (s != MI_OK) return s;
   }
+  const bool aligned = is_aligned(p->X, ldx);
   Plan pl;
-  s = choose_plan(p->m, p->n, is_aligned(p->X, ldx), p->tile, p->splits, &pl);
+  s = choose_plan(p->m, p->n, aligned, p->tile, p->splits, &pl);
   if (s != MI_OK) return s;
+  const uint8_t* X = p->X;
+  int64_t ld = ldx;
+  if (!aligned) {
+    ld = packed_pitch(p->n);
+    void* buf = nullptr;
+    s = scratch(st, 1, ws_slot, (size_t)p->m * (size_t)ld, &buf);
+    if (s != MI_OK) return s;
+    HIPCHK(launch_repack(p->X, p->m, p->n, ldx, (uint8_t*)buf, ld, st));
+    X = (const uint8_t*)buf;
+  }
   void* ws = nullptr;
   s = workspace(st, ws_slot, workspace_bytes(pl), &ws);
   if (s != MI_OK) return s;
-  const ProbDev P = make_probdev(p, ldx, pl, ws);
-  HIPCHK(launch_plain(pl.bt, P, st));
+  hipError_t e;
+  const int32_t* tiles = tile_table(pl.ntp, &e);
+  if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(e));
+  const ProbDev P = make_probdev(p, X, ld, pl, ws, tiles);
+  HIPCHK(launch_plain(pl.cfg, P, st));
   return MI_OK;
 }
 
@@ -307,7 +386,7 @@ static std::string batch_key(const mi_problem* probs, int64_t count, const std::
     const mi_problem& p = probs[d];
     snprintf(buf, sizeof buf, "%p,%lld,%lld,%lld,%p,%p,%p,%d,%g,%d,%d;", (const void*)p.X, (long long)p.m,
              (long long)p.n, (long long)p.ldx, (void*)p.out, (void*)p.n11_out, (void*)p.colsum_out, p.epilogue,
-             (double)p.fallback_tau, plans[d].bt, plans[d].splits);
+             (double)p.fallback_tau, plans[d].cfg, plans[d].splits);
     k += buf;
   }
   return k;
@@ -333,6 +412,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   DeviceInfo di;
   s = device_info(&di);
   if (s != MI_OK) return s;
+  std::vector<char> aligned(count);
+  for (int64_t d = 0; d < count; ++d) aligned[d] = is_aligned(probs[d].X, ldx[d]) ? 1 : 0;
 
   if (mode == MI_BATCH_PERSISTENT) {
     // Split each dataset's K range so that no unit is much larger than the
@@ -342,7 +423,7 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     for (int64_t d = 0; d < count; ++d) {
       if (probs[d].n == 0) continue;
       Plan p0;
-      s = choose_plan(probs[d].m, probs[d].n, is_aligned(probs[d].X, ldx[d]), probs[d].tile, 1, &p0);
+      s = choose_plan(probs[d].m, probs[d].n, aligned[d], probs[d].tile, 1, &p0);
       if (s != MI_OK) return s;
       total += (double)p0.ntiles * p0.bt * p0.bt * (double)probs[d].m;
       plans[d] = p0;
@@ -357,36 +438,57 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
         sp = (int)std::min<double>(std::ceil(unit / target), std::max<int64_t>(1, probs[d].m / 1024));
         sp = std::max(sp, 1);
       }
-      plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].bt, sp);
+      plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].cfg, sp);
     }
   } else {
     for (int64_t d = 0; d < count; ++d) {
       if (probs[d].n == 0) continue;
-      s = choose_plan(probs[d].m, probs[d].n, is_aligned(probs[d].X, ldx[d]), probs[d].tile, probs[d].splits, &plans[d]);
+      s = choose_plan(probs[d].m, probs[d].n, aligned[d], probs[d].tile, probs[d].splits, &plans[d]);
       if (s != MI_OK) return s;
     }
   }
 
-  // One workspace holding every dataset's split region.
-  std::vector<size_t> ws_off(count, 0);
-  size_t ws_total = 0;
+  // One split-K workspace and one repack buffer hold every dataset's region.
+  std::vector<size_t> ws_off(count, 0), rp_off(count, 0);
+  size_t ws_total = 0, rp_total = 0;
   for (int64_t d = 0; d < count; ++d) {
     if (probs[d].n == 0) continue;
     ws_off[d] = ws_total;
     ws_total += (workspace_bytes(plans[d]) + 255) & ~(size_t)255;
+    if (!aligned[d]) {
+      rp_off[d] = rp_total;
+      rp_total += ((size_t)probs[d].m * (size_t)packed_pitch(probs[d].n) + 255) & ~(size_t)255;
+    }
   }
   void* ws = nullptr;
+  void* rp = nullptr;
   s = workspace(st, 1, ws_total, &ws);
+  if (s != MI_OK) return s;
+  s = scratch(st, 1, 1, rp_total, &rp);
   if (s != MI_OK) return s;
   std::vector<ProbDev> P(count);
   for (int64_t d = 0; d < count; ++d) {
     if (probs[d].n == 0) continue;
-    P[d] = make_probdev(&probs[d], ldx[d], plans[d], ws ? (char*)ws + ws_off[d] : nullptr);
+    hipError_t e;
+    const int32_t* tiles = tile_table(plans[d].ntp, &e);
+    if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(e));
+    const uint8_t* X = aligned[d] ? probs[d].X : (const uint8_t*)rp + rp_off[d];
+    const int64_t ld = aligned[d] ? ldx[d] : packed_pitch(probs[d].n);
+    P[d] = make_probdev(&probs[d], X, ld, plans[d], ws ? (char*)ws + ws_off[d] : nullptr, tiles);
   }
+  auto repack_all = [&]() -> hipError_t {
+    for (int64_t d = 0; d < count; ++d) {
+      if (probs[d].n == 0 || aligned[d]) continue;
+      hipError_t e = launch_repack(probs[d].X, probs[d].m, probs[d].n, ldx[d], (uint8_t*)P[d].X, P[d].ldx, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
 
   if (mode == MI_BATCH_SEQUENTIAL) {
+    HIPCHK(repack_all());
     for (int64_t d = 0; d < count; ++d)
-      if (probs[d].n > 0) HIPCHK(launch_plain(plans[d].bt, P[d], st));
+      if (probs[d].n > 0) HIPCHK(launch_plain(plans[d].cfg, P[d], st));
     return MI_OK;
   }
 
@@ -401,18 +503,17 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     if (!exec) {
       hipGraph_t graph = nullptr;
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      for (int64_t d = 0; d < count; ++d) {
-        if (probs[d].n == 0) continue;
-        hipError_t e = launch_plain(plans[d].bt, P[d], st);
-        if (e != hipSuccess) {
-          hipGraph_t g2 = nullptr;
-          (void)hipStreamEndCapture(st, &g2);
-          if (g2) (void)hipGraphDestroy(g2);
-          return fail(MI_ERR_DEVICE, "capture launch %lld: %s", (long long)d, hipGetErrorString(e));
-        }
+      hipError_t e = repack_all();
+      for (int64_t d = 0; d < count && e == hipSuccess; ++d)
+        if (probs[d].n > 0) e = launch_plain(plans[d].cfg, P[d], st);
+      if (e != hipSuccess) {
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(st, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        return fail(MI_ERR_DEVICE, "launch during capture: %s", hipGetErrorString(e));
       }
       HIPCHK(hipStreamEndCapture(st, &graph));
-      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(MI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
       std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -426,23 +527,24 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     return MI_OK;
   }
 
-  // Persistent: work list sorted by decreasing unit cost, one launch per tile size.
-  std::vector<UnitRef> units[2];
+  // Persistent: work list sorted by decreasing unit rows, one launch per tile size.
+  std::vector<UnitRef> units[kNumCfg];
   for (int64_t d = 0; d < count; ++d) {
     if (probs[d].n == 0) continue;
-    const int b = plans[d].bt == 256 ? 1 : 0;
     for (int sp = 0; sp < plans[d].splits; ++sp)
-      for (int t = 0; t < plans[d].ntiles; ++t) units[b].push_back(UnitRef{(int32_t)d, t, sp, 0});
+      for (int t = 0; t < plans[d].ntiles; ++t) units[plans[d].cfg].push_back(UnitRef{(int32_t)d, t, sp, 0});
   }
-  for (int b = 0; b < 2; ++b) {
-    std::stable_sort(units[b].begin(), units[b].end(), [&](const UnitRef& x, const UnitRef& y) {
+  for (int c = 0; c < kNumCfg; ++c) {
+    std::stable_sort(units[c].begin(), units[c].end(), [&](const UnitRef& x, const UnitRef& y) {
       const int64_t rx = std::min<int64_t>(P[x.prob].kchunk, P[x.prob].m - (int64_t)x.split * P[x.prob].kchunk);
       const int64_t ry = std::min<int64_t>(P[y.prob].kchunk, P[y.prob].m - (int64_t)y.split * P[y.prob].kchunk);
       return rx > ry;
     });
   }
   const size_t probs_bytes = ((sizeof(ProbDev) * count) + 255) & ~(size_t)255;
-  const size_t units_bytes = ((sizeof(UnitRef) * (units[0].size() + units[1].size())) + 255) & ~(size_t)255;
+  size_t nunits = 0;
+  for (int c = 0; c < kNumCfg; ++c) nunits += units[c].size();
+  const size_t units_bytes = ((sizeof(UnitRef) * nunits) + 255) & ~(size_t)255;
   const size_t total = probs_bytes + units_bytes + 256;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -471,19 +573,23 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   if (!bb.copied) HIPCHK(hipEventCreateWithFlags(&bb.copied, hipEventDisableTiming));
   char* h = (char*)bb.host;
   std::memcpy(h, P.data(), sizeof(ProbDev) * count);
-  std::memcpy(h + probs_bytes, units[0].data(), sizeof(UnitRef) * units[0].size());
-  std::memcpy(h + probs_bytes + sizeof(UnitRef) * units[0].size(), units[1].data(), sizeof(UnitRef) * units[1].size());
+  size_t uoff = probs_bytes;
+  for (int c = 0; c < kNumCfg; ++c) {
+    std::memcpy(h + uoff, units[c].data(), sizeof(UnitRef) * units[c].size());
+    uoff += sizeof(UnitRef) * units[c].size();
+  }
   HIPCHK(hipMemcpyAsync(bb.dev, bb.host, probs_bytes + units_bytes, hipMemcpyHostToDevice, st));
   HIPCHK(hipEventRecord(bb.copied, st));
+  HIPCHK(repack_all());
   char* dv = (char*)bb.dev;
   const ProbDev* dP = (const ProbDev*)dv;
   const UnitRef* dU = (const UnitRef*)(dv + probs_bytes);
   int* head = (int*)(dv + probs_bytes + units_bytes);
-  const int grid0 = di.cus * di.pocc[0];
-  const int grid1 = di.cus * di.pocc[1];
-  HIPCHK(launch_persistent(128, dP, dU, (int)units[0].size(), head, std::min<int64_t>(grid0, units[0].size()), st));
-  HIPCHK(launch_persistent(256, dP, dU + units[0].size(), (int)units[1].size(), head + 1,
-                           std::min<int64_t>(grid1, units[1].size()), st));
+  for (int c = 0; c < kNumCfg; ++c) {
+    const int64_t grid = std::min<int64_t>((int64_t)di.cus * di.pocc[c], (int64_t)units[c].size());
+    HIPCHK(launch_persistent(c, dP, dU, (int)units[c].size(), head + c, (int)grid, st));
+    dU += units[c].size();
+  }
   return MI_OK;
 }
 
@@ -491,13 +597,17 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
 mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms) {
   if (m <= 0 || m > INT32_MAX || n <= 0 || n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "bad shape for tuning");
   if (ldx == 0) ldx = n;
-  if (ldx < n) return fail(MI_ERR_INVALID_ARG, "ldx < n");
+  if (ldx < n || ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "bad ldx for tuning");
   DeviceInfo di;
   mi_status s = device_info(&di);
   if (s != MI_OK) return s;
+  // The kernel's time does not depend on the data, and unaligned layouts are
+  // repacked to a packed pitch first, so time on a zero matrix of that pitch.
+  const bool aligned = ldx % 16 == 0;
+  const int64_t ld = aligned ? ldx : packed_pitch(n);
   uint8_t* X = nullptr;
   float* out = nullptr;
-  const size_t xbytes = (size_t)m * (size_t)ldx;
+  const size_t xbytes = (size_t)m * (size_t)ld;
   if (hipMalloc(&X, xbytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(MI_ERR_OUT_OF_MEMORY, "tuner: X allocation failed");
@@ -507,76 +617,69 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
     (void)hipFree(X);
     return fail(MI_ERR_OUT_OF_MEMORY, "tuner: out allocation failed");
   }
-  HIPCHK(hipMemset(X, 0, xbytes));
   hipStream_t st = nullptr;
-  HIPCHK(hipStreamCreate(&st));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  const bool aligned = is_aligned(X, ldx);
-  Tuned best{0, 0, 1e30};
-  const int bts[2] = {128, 256};
-  for (int bt : bts) {
-    const Plan p1 = make_plan(m, n, bt, 1);
-    const int slots = di.cus * di.occ[bt == 256 ? 1 : 0];
-    std::vector<int> cands;
-    const int64_t steps = cdiv(m, KT);
-    for (int sp : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256}) {
-      if (sp > steps) break;
-      cands.push_back(sp);
-    }
-    cands.push_back(heuristic_splits(m, p1.ntiles, slots));
-    std::sort(cands.begin(), cands.end());
-    cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
-    for (int sp : cands) {
-      const Plan pl = make_plan(m, n, bt, sp);
-      if ((double)pl.ntiles * pl.splits > 4.0e6) continue;
-      void* ws = nullptr;
-      s = workspace(st, 0, workspace_bytes(pl), &ws);
-      if (s != MI_OK) break;
-      mi_problem pr;
-      mi_problem_init(&pr, X, m, n, out);
-      pr.ldx = ldx;
-      const ProbDev P = make_probdev(&pr, ldx, pl, ws);
-      HIPCHK(launch_plain(bt, P, st));  // warm-up
-      float best_here = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {
-        HIPCHK(hipEventRecord(e0, st));
-        HIPCHK(launch_plain(bt, P, st));
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        best_here = std::min(best_here, ms);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  Tuned best{-1, 0, 1e30};
+  auto body = [&]() -> mi_status {
+    HIPCHK(hipMemset(X, 0, xbytes));
+    HIPCHK(hipStreamCreate(&st));
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    hipError_t te;
+    for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+      const Plan p1 = make_plan(m, n, cfg, 1);
+      const int64_t steps = cdiv(m, KT);
+      std::vector<int> cands;
+      for (int sp : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+        if (sp <= steps) cands.push_back(sp);
+      cands.push_back(heuristic_splits(m, p1, di.cus * di.occ[cfg]));
+      std::sort(cands.begin(), cands.end());
+      cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+      const int32_t* tiles = tile_table(p1.ntp, &te);
+      if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(te));
+      for (int sp : cands) {
+        const Plan pl = make_plan(m, n, cfg, sp);
+        if ((double)pl.ntiles * pl.splits > 4.0e6) continue;
+        void* ws = nullptr;
+        mi_status ss = workspace(st, 0, workspace_bytes(pl), &ws);
+        if (ss != MI_OK) return ss;
+        mi_problem pr;
+        mi_problem_init(&pr, X, m, n, out);
+        pr.ldx = ld;
+        const ProbDev P = make_probdev(&pr, X, ld, pl, ws, tiles);
+        HIPCHK(launch_plain(cfg, P, st));  // warm-up
+        float best_here = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          HIPCHK(hipEventRecord(e0, st));
+          HIPCHK(launch_plain(cfg, P, st));
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          best_here = std::min(best_here, ms);
+        }
+        if (best_here < best.ms) best = Tuned{cfg, pl.splits, best_here};
       }
-      if (best_here < best.ms) best = Tuned{bt, pl.splits, best_here};
     }
-    if (s != MI_OK) break;
+    return MI_OK;
+  };
+  s = body();
+  if (st) (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) {
+    release_scratch_of(st);
+    (void)hipStreamDestroy(st);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipStreamSynchronize(st);
-  {
-    // the tuner's workspace was keyed on its private stream: release it
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    auto it = g_ws.find(WsKey{dev, st, 0});
-    if (it != g_ws.end()) {
-      (void)hipFree(it->second.ptr);
-      g_ws.erase(it);
-    }
-  }
-  (void)hipStreamDestroy(st);
   (void)hipFree(X);
   (void)hipFree(out);
   if (s != MI_OK) return s;
-  if (best.bt == 0) return fail(MI_ERR_DEVICE, "tuner found no runnable configuration");
+  if (best.cfg < 0) return fail(MI_ERR_DEVICE, "tuner found no runnable configuration");
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[shape_key(m, n, aligned)] = best;
   }
-  if (tile) *tile = best.bt == 256 ? MI_TILE_256 : MI_TILE_128;
+  if (tile) *tile = best.cfg == 1 ? MI_TILE_256 : MI_TILE_128;
   if (splits) *splits = best.splits;
   if (best_ms) *best_ms = best.ms;
   return MI_OK;
@@ -589,7 +692,7 @@ mi_status tuner_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& kv : g_tuned)
     fprintf(f, "{\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %.6f}\n", kv.first.mb,
-            kv.first.nb, kv.first.aligned, kv.second.bt, kv.second.splits, kv.second.ms);
+            kv.first.nb, kv.first.aligned, cfg_tile(kv.second.cfg), kv.second.splits, kv.second.ms);
   fclose(f);
   return MI_OK;
 }
@@ -604,9 +707,11 @@ mi_status tuner_load(const char* path) {
   while (fgets(line, sizeof line, f)) {
     ShapeKey k;
     Tuned t;
+    int tile = 0;
     if (sscanf(line, " {\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %lf}", &k.mb,
-               &k.nb, &k.aligned, &t.bt, &t.splits, &t.ms) == 6 &&
-        (t.bt == 128 || t.bt == 256) && t.splits >= 1) {
+               &k.nb, &k.aligned, &tile, &t.splits, &t.ms) == 6 &&
+        (tile == 128 || tile == 256) && t.splits >= 1) {
+      t.cfg = tile == 256 ? 1 : 0;
       g_tuned[k] = t;
       ++nread;
     }
@@ -672,7 +777,7 @@ mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* spl
   Plan pl;
   mi_status s = choose_plan(m, std::max<int64_t>(n, 1), ldx % 16 == 0, 0, 0, &pl);
   if (s != MI_OK) return s;
-  if (tile) *tile = pl.bt == 256 ? MI_TILE_256 : MI_TILE_128;
+  if (tile) *tile = pl.cfg == 1 ? MI_TILE_256 : MI_TILE_128;
   if (splits) *splits = pl.splits;
   return MI_OK;
 }

@@ -2,22 +2,27 @@
 //
 // One work unit = (dataset, output tile (I, J) with I <= J, K-split s).  A unit
 //   1. streams its rows [k0, k1) of the two column panels X[:, I] and X[:, J]
-//      from HBM through LDS (double-buffered, one barrier per 64-row stage),
-//      transposing 4x4 byte blocks in registers so that each column's samples
-//      are contiguous, as the int8 matrix-core operands need;
-//   2. accumulates the 1-1 counts n11 = X_I^T X_J (the Gram product of
+//      from HBM into a 4-stage LDS ring with buffer->LDS DMA loads (no
+//      registers, no VALU); rows past k1 come back as zeros from the buffer
+//      range check, so the loop has no data-dependent branches;
+//   2. reads its int8 matrix-core operands with ds_read_b64_tr_b8, which
+//      transposes the sample-major panel (row = sample, as in X) into the
+//      operand layout (each lane: 8 consecutive samples of one column);
+//   3. accumulates the 1-1 counts n11 = X_I^T X_J (the Gram product of
 //      Section 2 step 2 / Section 3, the only matrix product of the method)
 //      with v_mfma_i32_16x16x64_i8, exact in int32;
-//   3. accumulates the column sums c_I, c_J of its rows with v_dot4_u32_u8 on
-//      the already-transposed bytes (Section 2 step 3 / Section 3.1 "Term 2");
-//   4. with several K-splits, adds its partial counts into a per-tile int32
+//   4. accumulates the column sums c_I, c_J of its rows with v_dot4_u32_u8 on
+//      the operand registers (Section 2 step 3 / Section 3.1 "Term 2");
+//   5. with several K-splits, adds its partial counts into a per-tile int32
 //      workspace; the last unit to arrive at a tile reads the totals back,
 //      clears the workspace, and alone runs the epilogue;
-//   5. epilogue: derives n10, n01, n00 from n11, c and m (Section 3.1,
+//   6. epilogue: derives n10, n01, n00 from n11, c and m (Section 3.1,
 //      Eq. 6/7), evaluates MI (Eq. 2/3) per element in FP32 (FP64 on demand)
 //      and writes the tile and its mirror.
-//
 // Only upper-triangular tiles exist; the mirror write fills the lower one.
+//
+// Requirements checked on the host: X 16-byte aligned, ldx % 16 == 0 and
+// 64 * ldx < 2^31 (other layouts are repacked first).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,11 +30,34 @@
 
 namespace mi {
 
+typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
+#define MI_LDS __attribute__((address_space(3)))
 
-constexpr int KT = 64;          // rows (samples) per LDS stage = one MFMA K step
-constexpr int NTHREADS = 256;   // 4 waves
-constexpr int HALF = NTHREADS / 2;
+constexpr int KT = 64;  // samples per stage = one MFMA K step
+
+// Tile configuration: BT x BT output tile, WGM x WGN waves, NS-stage LDS ring.
+template <int BT_, int WGM_, int WGN_, int NS_>
+struct Cfg {
+  static constexpr int BT = BT_, WGM = WGM_, WGN = WGN_, NS = NS_;
+  static constexpr int NWAVES = WGM * WGN;
+  static constexpr int NT = 64 * NWAVES;
+  static constexpr int WTM = BT / WGM, WTN = BT / WGN;  // wave tile
+  static constexpr int FM = WTM / 16, FN = WTN / 16;    // 16x16 fragments
+  static constexpr int PANEL = BT * KT;                 // bytes of one panel stage
+  static constexpr int STAGE = 2 * PANEL;               // panel I then panel J
+  static constexpr int REGIONS = STAGE / 1024;          // 1 KB DMA regions
+  static constexpr int LOADS = REGIONS / NWAVES;        // DMA instructions per wave per stage
+  static constexpr int ROWS_PER_REGION = 1024 / BT;
+  static constexpr int SEGS = BT / 16;                  // 16-byte segments per row
+  static constexpr int STRIP = 16 * WTN;                // epilogue strip elements per wave
+  static constexpr int COL_OFF = NS * STAGE;            // column sums after the ring
+  static constexpr int LDS_BYTES = NS * STAGE + 2 * BT * 4 + 16;
+  static_assert(REGIONS % NWAVES == 0, "DMA regions must split evenly over waves");
+  static_assert(NWAVES * 2 * STRIP * 4 <= NS * STAGE, "epilogue strips must fit in the ring");
+};
+using Cfg128 = Cfg<128, 2, 2, 4>;  // 4 waves of 64 x 64; 65 KB LDS, 2 workgroups per CU
+using Cfg256 = Cfg<256, 2, 4, 4>;  // 8 waves of 128 x 64; 130 KB LDS, 1 workgroup per CU
 
 // Everything a unit needs to know about its dataset.
 struct ProbDev {
@@ -42,13 +70,15 @@ struct ProbDev {
   int32_t* ws_n11;      // splits > 1: ntiles * BT * BT int32, all zero between calls
   int32_t* ws_col;      // splits > 1: ntiles * 2 * BT int32
   int32_t* counters;    // splits > 1: ntiles int32
+  const int32_t* tiles; // tile order: ntiles entries of (I << 16) | J
   int32_t ntp;          // panels = ceil(n / BT)
   int32_t ntiles;       // ntp (ntp + 1) / 2
   int32_t splits;
   int32_t kchunk;       // rows per split, a multiple of KT
   int32_t epi;          // mi_epilogue
   float tau;
-  int32_t aligned;      // X 16-byte aligned and ldx % 16 == 0
+  int32_t tiles_per_xcd;  // plain launch: tiles owned by each of the 8 XCDs
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -61,17 +91,17 @@ struct ProbDev {
 __device__ __forceinline__ float cell32(int nxy, int nx, int ny, float fm) {
 #pragma clang fp contract(off)
   if (nxy <= 0) return 0.0f;                      // 0 log 0 = 0
-  float fn = (float)nxy;
-  float num = fn * fm;                            // n_xy * m
-  float den = (float)nx * (float)ny;              // n_x * n_y
+  const float fn = (float)nxy;
+  const float num = fn * fm;                      // n_xy * m
+  const float den = (float)nx * (float)ny;        // n_x * n_y
   return fn * __log2f(__fdividef(num, den));
 }
 
 __device__ __forceinline__ double cell64(int nxy, int nx, int ny, int m) {
 #pragma clang fp contract(off)
   if (nxy <= 0) return 0.0;
-  double num = (double)((int64_t)nxy * (int64_t)m);   // exact below 2^53
-  double den = (double)((int64_t)nx * (int64_t)ny);
+  const double num = (double)((int64_t)nxy * (int64_t)m);  // exact below 2^53
+  const double den = (double)((int64_t)nx * (int64_t)ny);
   return (double)nxy * log2(num / den);
 }
 
@@ -88,11 +118,11 @@ __device__ __forceinline__ float mi_value64(int m, int ci, int cj, int n11) {
 __device__ __forceinline__ float mi_value(int m, int ci, int cj, int n11, int epi, float tau) {
 #pragma clang fp contract(off)
   if (epi == 2) return mi_value64(m, ci, cj, n11);
-  const int n10 = ci - n11;          // X_i = 1, X_j = 0
-  const int n01 = cj - n11;          // X_i = 0, X_j = 1
-  const int ni0 = m - ci;            // marginal count of X_i = 0
-  const int nj0 = m - cj;            // marginal count of X_j = 0
-  const int n00 = ni0 - n01;         // = m - c_i - c_j + n11, without overflow
+  const int n10 = ci - n11;   // X_i = 1, X_j = 0
+  const int n01 = cj - n11;   // X_i = 0, X_j = 1
+  const int ni0 = m - ci;     // marginal count of X_i = 0
+  const int nj0 = m - cj;     // marginal count of X_j = 0
+  const int n00 = ni0 - n01;  // = m - c_i - c_j + n11, without overflow
   const float fm = (float)m;
   const float t11 = cell32(n11, ci, cj, fm);
   const float t00 = cell32(n00, ni0, nj0, fm);
@@ -104,274 +134,189 @@ __device__ __forceinline__ float mi_value(int m, int ci, int cj, int n11, int ep
 }
 
 // ---------------------------------------------------------------------------
-// LDS layout of one staged panel: BT columns x 64 samples, no padding.  Four
-// consecutive columns share one 256-byte bank row; inside it the 16 slots of
-// 16 bytes (4 columns x 4 sample chunks g) are permuted by
-//     slot = 4 * (t ^ g ^ 2b) + (q ^ g),   t = col & 3,
-//     q = ((col >> 2) ^ (col >> 4)) & 3,   b = (col >> 6) & 1,
-// which makes both access patterns conflict-free on the 64 banks:
-//   * operand reads: 16 lanes read 16 consecutive columns at one chunk g;
-//   * staging writes: 64 lanes write one dword each for 8 column chunks x
-//     8 row quads (the mapping used by stage_store below).
+// LDS layout of one staged panel: 64 rows (samples) of BT bytes, row-major as
+// in X, with the 16-byte segments of row r permuted by  seg' = seg ^ f(r).
+// A transposed operand read makes each 16-lane group fetch one segment from 8
+// rows (two lanes per segment); the two groups of a half-wave use rows
+// {g*16 .. g*16+7} and {(g+1)*16 .. +7}.  f spreads those 16 rows over all 64
+// banks; the DMA writes are contiguous 1 KB runs and conflict-free anyway.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int lds_off(int col, int g) {
-  const int t = col & 3;
-  const int q = ((col >> 2) ^ (col >> 4)) & 3;
-  const int b = (col >> 6) & 1;
-  const int slot = 4 * (t ^ g ^ (b << 1)) + (q ^ g);
-  return ((col >> 2) << 8) + (slot << 4);
+template <int BT>
+__device__ __forceinline__ int seg_swz(int row) {
+  if (BT == 256) return (row & 7) | (((row >> 4) & 1) << 3);     // 16 segments per row
+  return ((row >> 1) & 3) | (((row >> 4) & 1) << 2);             // 8 segments, 2 rows per bank row
 }
 
-// Staging work split: a panel of BT columns x 64 rows is 16-column x 4-row
-// chunks; chunk q of a panel goes to thread (q mod HALF) of that panel's half
-// of the workgroup.  Within a block of 128 chunks: cc = q % 8 selects 16
-// columns, rq = (q / 8) % 16 selects 4 rows; block q / 128 adds 128 columns.
+// Byte offset (inside one panel) read by `lane` for the first half (samples
+// g*16 .. g*16+7) of the operand fragment whose 16 columns start at segment s;
+// the second half (samples +8) is 8 rows further, i.e. + 8 * BT bytes.
 template <int BT>
-struct Staging {
-  static constexpr int CHUNKS = BT / 16 * (KT / 4);
-  static constexpr int G = CHUNKS / HALF;       // chunks per thread
-  static_assert(G >= 1 && CHUNKS % HALF == 0, "tile / thread mismatch");
-  __device__ static __forceinline__ int chunk_col(int q) { return ((q & 7) + 8 * (q >> 7)) * 16; }
-  __device__ static __forceinline__ int chunk_row(int q) { return ((q >> 3) & 15) * 4; }
-};
-
-__device__ __forceinline__ uint32_t keep_mask(int valid, int w) {
-  // bytes of dword w (columns 4w..4w+3 of a 16-byte chunk) with index < valid
-  const int k = min(max(valid - 4 * w, 0), 4);
-  return (uint32_t)((1ull << (8 * k)) - 1ull);
+__device__ __forceinline__ int frag_off(int s, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  const int row = g * 16 + (j >> 1);
+  return row * BT + ((s ^ seg_swz<BT>(row)) << 4) + ((j & 1) << 3);
 }
 
-typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-
-// Per-thread staging context, fixed for a whole unit.
-template <int BT>
-struct StageCtx {
-  int voff[Staging<BT>::G];     // byte offset of the chunk's first row inside a stage
-  int col[Staging<BT>::G];      // first matrix column of the chunk
-  int row[Staging<BT>::G];      // first row of the chunk inside a stage (0..60)
-  uint32_t cm[Staging<BT>::G][4];  // keep-masks for columns >= n
-};
-
-template <int BT>
-__device__ __forceinline__ void stage_ctx(StageCtx<BT>& c, const ProbDev& P, int colbase, int p) {
+// Read the fragments of one stage: NF fragments at LDS byte addresses
+// base + a[f] (plus 8 * BT for the second half).  The wait for the reads is
+// inside the same asm block, so every output is complete when the block ends.
+template <int BT, int NF>
+__device__ __forceinline__ void read_frags(v4i (&fr)[NF], const uint32_t (&a)[NF], uint32_t base) {
+  static_assert(NF % 4 == 0, "fragments are read four at a time");
 #pragma unroll
-  for (int gi = 0; gi < Staging<BT>::G; ++gi) {
-    const int q = p + gi * HALF;
-    c.col[gi] = colbase + Staging<BT>::chunk_col(q);
-    c.row[gi] = Staging<BT>::chunk_row(q);
-    const int valid = min(P.n - c.col[gi], 16);
-    // A chunk entirely right of column n reads at an offset past every stage's
-    // buffer range, which the hardware returns as zeros.
-    c.voff[gi] = valid > 0 ? c.row[gi] * (int)P.ldx + c.col[gi] : KT * (int)P.ldx;
+  for (int f = 0; f < NF; f += 4) {
+    v2i x[8];
+    asm volatile(
+        "ds_read_b64_tr_b8 %0, %8\n\t"
+        "ds_read_b64_tr_b8 %1, %8 offset:%12\n\t"
+        "ds_read_b64_tr_b8 %2, %9\n\t"
+        "ds_read_b64_tr_b8 %3, %9 offset:%12\n\t"
+        "ds_read_b64_tr_b8 %4, %10\n\t"
+        "ds_read_b64_tr_b8 %5, %10 offset:%12\n\t"
+        "ds_read_b64_tr_b8 %6, %11\n\t"
+        "ds_read_b64_tr_b8 %7, %11 offset:%12\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]), "=&v"(x[7])
+        : "v"(base + a[f]), "v"(base + a[f + 1]), "v"(base + a[f + 2]), "v"(base + a[f + 3]), "i"(8 * BT)
+        : "memory");
 #pragma unroll
-    for (int w = 0; w < 4; ++w) c.cm[gi][w] = keep_mask(valid, w);
+    for (int q = 0; q < 4; ++q) fr[f + q] = v4i{x[2 * q].x, x[2 * q].y, x[2 * q + 1].x, x[2 * q + 1].y};
   }
 }
 
-// Global -> registers for the stage starting at row ks (rows >= kend read as 0).
-// Aligned layout: raw buffer loads whose range ends at row min(kend, ks + KT),
-// so out-of-range rows come back as zeros without any branch; the loads of a
-// stage issue back to back and only the consumer waits for them.
-template <int BT, bool ALIGNED>
-__device__ __forceinline__ void stage_load(uint4 (&r)[Staging<BT>::G][4], const ProbDev& P, const StageCtx<BT>& c,
-                                           int ks, int kend) {
-  if (ALIGNED) {
-    // ks and kend are uniform across the workgroup; readfirstlane keeps the
-    // descriptor in scalar registers (no per-lane waterfall around the loads).
-    const int rows = __builtin_amdgcn_readfirstlane(max(0, min(kend - ks, KT)));
-    const int ld = __builtin_amdgcn_readfirstlane((int)P.ldx);
-    const uint64_t base = (uint64_t)(P.X + (int64_t)min(ks, P.m - 1) * P.ldx);
-    const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-    const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-    __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(((uint64_t)bhi << 32) | blo), 0, rows * ld, 0x00020000);
-#pragma unroll
-    for (int gi = 0; gi < Staging<BT>::G; ++gi)
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        // the whole offset goes in the vector operand, which the range check covers
-        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, c.voff[gi] + rr * ld, 0, 0);
-        r[gi][rr] = make_uint4(v.x, v.y, v.z, v.w);
-      }
-  } else {
-#pragma unroll
-    for (int gi = 0; gi < Staging<BT>::G; ++gi) {
-      const int valid = min(P.n - c.col[gi], 16);
-#pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int row = ks + c.row[gi] + rr;
-        uint32_t w4[4] = {0u, 0u, 0u, 0u};
-        if (row < kend && valid > 0) {
-          const uint8_t* src = P.X + (int64_t)row * P.ldx + c.col[gi];
-#pragma unroll
-          for (int b = 0; b < 16; ++b)
-            if (b < valid) w4[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
-        }
-        r[gi][rr] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
-      }
-    }
-  }
+__device__ __forceinline__ uint32_t dot_ones(const v4i& v, uint32_t acc) {
+  acc = __builtin_amdgcn_udot4((uint32_t)v.x, 0x01010101u, acc, false);
+  acc = __builtin_amdgcn_udot4((uint32_t)v.y, 0x01010101u, acc, false);
+  acc = __builtin_amdgcn_udot4((uint32_t)v.z, 0x01010101u, acc, false);
+  acc = __builtin_amdgcn_udot4((uint32_t)v.w, 0x01010101u, acc, false);
+  return acc;
 }
 
-__device__ __forceinline__ uint32_t u4get(const uint4& v, int w) {
-  return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+__device__ __forceinline__ uint32_t sgpr(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Buffer descriptor for the rows [ks, min(ks + KT, kend)) of X: reads at byte
+// offsets past that range return zeros.  ks and kend are workgroup-uniform.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stage_rsrc(const ProbDev& P, int ks, int kend) {
+  const int rows = max(0, min(kend - ks, KT));
+  const uint64_t base = (uint64_t)(P.X + (int64_t)min(ks, P.m - 1) * P.ldx);
+  const uint32_t lo = sgpr((uint32_t)base), hi = sgpr((uint32_t)(base >> 32));
+  const int nrec = (int)sgpr((uint32_t)(rows * (int)P.ldx));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), 0, nrec, 0x00020000);
 }
 
-// Registers -> LDS for one stage of one panel: mask columns >= n, 4x4 byte
-// transposes so that a dword holds 4 consecutive samples of one column, and
-// column-sum updates.
-template <int BT>
-__device__ __forceinline__ void stage_store(uint8_t* sbuf, const uint4 (&r)[Staging<BT>::G][4], const StageCtx<BT>& c,
-                                            uint32_t (&csum)[Staging<BT>::G][16]) {
-#pragma unroll
-  for (int gi = 0; gi < Staging<BT>::G; ++gi) {
-    const int c0 = c.col[gi] & (BT - 1);          // column inside the panel
-    const int rq = c.row[gi] >> 2;                // row quad 0..15
-    const int g = rq >> 2, d = rq & 3;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const uint32_t m = c.cm[gi][w];
-      const uint32_t a = u4get(r[gi][0], w) & m, b = u4get(r[gi][1], w) & m;
-      const uint32_t cc = u4get(r[gi][2], w) & m, e = u4get(r[gi][3], w) & m;
-      const uint32_t x0 = __builtin_amdgcn_perm(b, a, 0x05010400u);  // a0 b0 a1 b1
-      const uint32_t x1 = __builtin_amdgcn_perm(b, a, 0x07030602u);  // a2 b2 a3 b3
-      const uint32_t y0 = __builtin_amdgcn_perm(e, cc, 0x05010400u); // c0 e0 c1 e1
-      const uint32_t y1 = __builtin_amdgcn_perm(e, cc, 0x07030602u); // c2 e2 c3 e3
-      uint32_t o[4];
-      o[0] = __builtin_amdgcn_perm(y0, x0, 0x05040100u);  // column 4w+0, rows 0..3
-      o[1] = __builtin_amdgcn_perm(y0, x0, 0x07060302u);  // column 4w+1
-      o[2] = __builtin_amdgcn_perm(y1, x1, 0x05040100u);  // column 4w+2
-      o[3] = __builtin_amdgcn_perm(y1, x1, 0x07060302u);  // column 4w+3
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int col = c0 + 4 * w + t;
-        *reinterpret_cast<uint32_t*>(sbuf + lds_off(col, g) + 4 * d) = o[t];
-        csum[gi][4 * w + t] = __builtin_amdgcn_udot4(o[t], 0x01010101u, csum[gi][4 * w + t], false);
-      }
-    }
-  }
+// Decode an upper-triangular tile from the order table.
+__device__ __forceinline__ void tile_ij(const ProbDev& P, int t, int& I, int& J) {
+  const int v = P.tiles[t];
+  I = v >> 16;
+  J = v & 0xFFFF;
 }
 
-// Tile geometry for the 4-wave workgroup: waves in a 2 x 2 grid, each wave
-// owns a (BT/2) x (BT/2) block made of 16 x 16 MFMA fragments.
-template <int BT>
-struct TileGeom {
-  static constexpr int WT = BT / 2;
-  static constexpr int F = WT / 16;          // fragments per side of a wave block
-  static constexpr int PANEL_BYTES = BT * KT;
-  static constexpr int STAGE_BYTES = 2 * PANEL_BYTES;  // panel I then panel J
-  static constexpr int LDS_BYTES = 2 * STAGE_BYTES + 2 * BT * 4 + 16;
-  static_assert(4 * 2 * 16 * WT * 4 <= 2 * STAGE_BYTES, "epilogue strips must fit in the stage buffers");
-};
-
-// Decode upper-triangular tile t (row-major over I <= J) into (I, J).
-__device__ __forceinline__ void tile_ij(int t, int ntp, int& I, int& J) {
-  int i = 0;
-  int rem = t;
-  while (rem >= ntp - i) { rem -= ntp - i; ++i; }
-  I = i;
-  J = i + rem;
-}
-
-// One work unit.  smem must hold TileGeom<BT>::LDS_BYTES bytes, 16-aligned.
-template <int BT, bool ALIGNED>
+// One work unit.  smem: C::LDS_BYTES bytes, 16-aligned.
+template <class C>
 __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
-  using TG = TileGeom<BT>;
-  using ST = Staging<BT>;
-  constexpr int F = TG::F;
+#if defined(__HIP_DEVICE_COMPILE__)  // device-only body (gfx950 builtins and asm)
+  constexpr int BT = C::BT, FM = C::FM, FN = C::FN;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wave = (int)sgpr((uint32_t)(tid >> 6));  // wave-uniform: scalar branches on it
+  const int wm = wave / C::WGN, wn = wave % C::WGN;
 
   int I, J;
-  tile_ij(t, P.ntp, I, J);
+  tile_ij(P, t, I, J);
   const bool diag = (I == J);
   const int k0 = s * P.kchunk;
   const int k1 = min(P.m, k0 + P.kchunk);
-  const int nsteps = (k1 > k0) ? (k1 - k0 + KT - 1) / KT : 0;
+  const int nsteps = (k1 - k0 + KT - 1) / KT;
 
-  int32_t* sColA = reinterpret_cast<int32_t*>(smem + 2 * TG::STAGE_BYTES);
+  int32_t* sColA = reinterpret_cast<int32_t*>(smem + C::COL_OFF);
   int32_t* sColB = sColA + BT;
   int32_t* sFlag = sColB + BT;
+  for (int c = tid; c < 2 * BT; c += C::NT) sColA[c] = 0;
 
-  // Staging role: threads [0, HALF) stage panel I, [HALF, 2 HALF) panel J (on a
-  // diagonal tile both halves stage the same panel, which keeps the pipeline
-  // free of divergent branches).
-  const int half = tid / HALF;
-  const int p = tid % HALF;
-  const int colbase = (half == 0 ? I : J) * BT;
-  const int soff = half * TG::PANEL_BYTES;
-  StageCtx<BT> ctx;
-  stage_ctx<BT>(ctx, P, colbase, p);
-
-  for (int c = tid; c < 2 * BT; c += NTHREADS) sColA[c] = 0;
-
-  v4i acc[F][F];
+  // DMA source offsets of this lane's LOADS regions (fixed for the unit).
+  // Region R = i * NWAVES + wave holds ROWS_PER_REGION rows of one panel;
+  // lane l of it lands at R * 1024 + 16 l, i.e. row R' * RPR + l / SEGS at
+  // physical segment l % SEGS, which holds logical segment (l % SEGS) ^ f(row).
+  int voff[C::LOADS];
+  uint32_t ldsoff[C::LOADS];
 #pragma unroll
-  for (int a = 0; a < F; ++a)
+  for (int i = 0; i < C::LOADS; ++i) {
+    const int R = i * C::NWAVES + wave;
+    const int panel = R / (C::REGIONS / 2);
+    const int row = (R % (C::REGIONS / 2)) * C::ROWS_PER_REGION + lane / C::SEGS;
+    const int seg = (lane % C::SEGS) ^ seg_swz<BT>(row);
+    const int col0 = (panel == 0 ? I : J) * BT;
+    voff[i] = row * (int)P.ldx + col0 + 16 * seg;
+    ldsoff[i] = (uint32_t)R * 1024u;
+  }
+  const uint32_t lds_base = (uint32_t)(uintptr_t)(MI_LDS void*)smem;
+  auto dma_stage = [&](int ks, int buf) {
+    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(P, ks, k1);
 #pragma unroll
-    for (int b = 0; b < F; ++b) acc[a][b] = v4i{0, 0, 0, 0};
-
-  uint32_t csum[ST::G][16];
-#pragma unroll
-  for (int gi = 0; gi < ST::G; ++gi)
-#pragma unroll
-    for (int c = 0; c < 16; ++c) csum[gi][c] = 0u;
-
-  const int g = lane >> 4;
-  auto mma_stage = [&](const uint8_t* cur) {
-    const uint8_t* sA = cur;
-    const uint8_t* sB = cur + TG::PANEL_BYTES;
-    v4i fa[F], fb[F];
-#pragma unroll
-    for (int a = 0; a < F; ++a)
-      fa[a] = *reinterpret_cast<const v4i*>(sA + lds_off(wm * TG::WT + a * 16 + (lane & 15), g));
-#pragma unroll
-    for (int b = 0; b < F; ++b)
-      fb[b] = *reinterpret_cast<const v4i*>(sB + lds_off(wn * TG::WT + b * 16 + (lane & 15), g));
-#pragma unroll
-    for (int a = 0; a < F; ++a)
-#pragma unroll
-      for (int b = 0; b < F; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    for (int i = 0; i < C::LOADS; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rs, (MI_LDS void*)(uintptr_t)(lds_base + (uint32_t)buf * C::STAGE + ldsoff[i]), 16, voff[i], 0, 0, 0);
   };
 
-  // Two register sets: during step s the loads of step s + 2 are in flight
-  // while step s + 1 waits in the other set, so each load has two steps of
-  // matrix work to hide behind.  Loads past the unit's rows are zeroed, not
-  // skipped, so the loop body has no data-dependent branches.
-  uint4 r0[ST::G][4], r1[ST::G][4];
-  stage_load<BT, ALIGNED>(r0, P, ctx, k0, k1);
-  stage_load<BT, ALIGNED>(r1, P, ctx, k0 + KT, k1);
-  stage_store<BT>(smem + soff, r0, ctx, csum);
-  __syncthreads();
-
-  // An even number of steps, no exits inside the body: a stage past the
-  // unit's last row loads as zeros and adds nothing to the counts.
-  for (int step = 0; step < nsteps; step += 2) {
-    // even step: compute buffer 0, refill r0 with step + 2, store r1 (step + 1) into buffer 1
-    stage_load<BT, ALIGNED>(r0, P, ctx, k0 + (step + 2) * KT, k1);
-    mma_stage(smem);
-    stage_store<BT>(smem + TG::STAGE_BYTES + soff, r1, ctx, csum);
-    __syncthreads();
-    // odd step: compute buffer 1, refill r1 with step + 3, store r0 (step + 2) into buffer 0
-    stage_load<BT, ALIGNED>(r1, P, ctx, k0 + (step + 3) * KT, k1);
-    mma_stage(smem + TG::STAGE_BYTES);
-    stage_store<BT>(smem + soff, r0, ctx, csum);
-    __syncthreads();
-  }
-
-  // Column sums of this unit's rows: reduce the per-thread partials in LDS.
-  {
-    int32_t* dst = (half == 0) ? sColA : sColB;
+  // Operand read offsets (inside a stage) for this lane's fragments.
+  uint32_t aoff[FM], boff[FN];
 #pragma unroll
-    for (int gi = 0; gi < Staging<BT>::G; ++gi) {
-      const int c0 = ctx.col[gi] & (BT - 1);
+  for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off<BT>((wm * C::WTM) / 16 + a, lane);
 #pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (csum[gi][c]) atomicAdd(&dst[c0 + c], (int32_t)csum[gi][c]);
+  for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off<BT>((wn * C::WTN) / 16 + b, lane));
+
+  v4i acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+  uint32_t csA[FM], csB[FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a) csA[a] = 0u;
+#pragma unroll
+  for (int b = 0; b < FN; ++b) csB[b] = 0u;
+  const bool sumA = (wn == 0), sumB = (wm == 0);
+
+  // Prologue: stages 0 .. NS-2 in flight.
+#pragma unroll
+  for (int st = 0; st < C::NS - 1; ++st) dma_stage(k0 + st * KT, st);
+
+  for (int step = 0; step < nsteps; ++step) {
+    // This wave's DMA for stage `step` is done once at most (NS-2) stages of
+    // later loads are outstanding; the barrier then covers every wave, and
+    // also guarantees that all waves finished reading the buffer refilled next.
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"i"((C::NS - 2) * C::LOADS) : "memory");
+    dma_stage(k0 + (step + C::NS - 1) * KT, (step + C::NS - 1) % C::NS);
+    const uint32_t sb = lds_base + (uint32_t)(step % C::NS) * C::STAGE;
+    v4i fa[FM], fb[FN];
+    read_frags<BT, FM>(fa, aoff, sb);
+    read_frags<BT, FN>(fb, boff, sb);
+    if (sumA) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a) csA[a] = dot_ones(fa[a], csA[a]);
     }
+    if (sumB) {
+#pragma unroll
+      for (int b = 0; b < FN; ++b) csB[b] = dot_ones(fb[b], csB[b]);
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+  // Drain the DMA of stages past the end before the ring is reused.
+  asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+
+  // Column sums of this unit's rows: the four lane groups of a wave hold
+  // partial sums of the same 16 columns; combine them in LDS.
+  if (sumA) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a) atomicAdd(&sColA[wm * C::WTM + a * 16 + (lane & 15)], (int)csA[a]);
+  }
+  if (sumB) {
+#pragma unroll
+    for (int b = 0; b < FN; ++b) atomicAdd(&sColB[wn * C::WTN + b * 16 + (lane & 15)], (int)csB[b]);
   }
   __syncthreads();
 
@@ -380,17 +325,17 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
     int32_t* wsn = P.ws_n11 + (int64_t)t * BT * BT;
     int32_t* wsc = P.ws_col + (int64_t)t * 2 * BT;
 #pragma unroll
-    for (int a = 0; a < F; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int b = 0; b < F; ++b)
+      for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = wm * TG::WT + a * 16 + 4 * (lane >> 4) + r;
-          const int col = wn * TG::WT + b * 16 + (lane & 15);
+          const int row = wm * C::WTM + a * 16 + 4 * (lane >> 4) + r;
+          const int col = wn * C::WTN + b * 16 + (lane & 15);
           const int v = acc[a][b][r];
           if (v) __hip_atomic_fetch_add(&wsn[row * BT + col], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-    for (int c = tid; c < 2 * BT; c += NTHREADS) {
+    for (int c = tid; c < 2 * BT; c += C::NT) {
       const int v = sColA[c];
       if (v) __hip_atomic_fetch_add(&wsc[c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -405,19 +350,19 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // Last arrival: totals back into registers and LDS, then clear the workspace.
 #pragma unroll
-    for (int a = 0; a < F; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int b = 0; b < F; ++b)
+      for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = wm * TG::WT + a * 16 + 4 * (lane >> 4) + r;
-          const int col = wn * TG::WT + b * 16 + (lane & 15);
+          const int row = wm * C::WTM + a * 16 + 4 * (lane >> 4) + r;
+          const int col = wn * C::WTN + b * 16 + (lane & 15);
           int32_t* w = &wsn[row * BT + col];
           acc[a][b][r] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(w, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     __syncthreads();
-    for (int c = tid; c < 2 * BT; c += NTHREADS) {
+    for (int c = tid; c < 2 * BT; c += C::NT) {
       sColA[c] = __hip_atomic_load(&wsc[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&wsc[c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -426,34 +371,34 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
   }
 
   // Epilogue: derived cells, MI, tile and mirror write-back.  Each wave moves
-  // its accumulators through LDS (the stage buffers are free now) one 16-row
-  // strip at a time: pass 1 reads the strip row-wise, evaluates MI once per
-  // element and writes the tile rows (consecutive lanes, consecutive j); pass 2
-  // reads the strip column-wise and writes the mirror rows (consecutive i).
+  // its accumulators through LDS (the ring is free now) one 16-row strip at a
+  // time: pass 1 reads the strip row-wise, evaluates MI once per element and
+  // writes the tile rows (consecutive lanes, consecutive j); pass 2 reads the
+  // strip column-wise and writes the mirror rows (consecutive i).
   const int n = P.n;
   const int64_t ln = n;
   if (diag && P.colsum_out) {
-    for (int c = tid; c < BT; c += NTHREADS) {
+    for (int c = tid; c < BT; c += C::NT) {
       const int i = I * BT + c;
       if (i < n) P.colsum_out[i] = sColA[c];
     }
   }
-  constexpr int WT = TG::WT;
-  constexpr int STRIP = 16 * WT;                       // elements per strip
+  constexpr int WTN = C::WTN;
+  constexpr int STRIP = C::STRIP;
   int32_t* sN = reinterpret_cast<int32_t*>(smem) + wave * 2 * STRIP;
   float* sM = reinterpret_cast<float*>(sN + STRIP);
-  const int ibase = I * BT + wm * WT;
-  const int jbase = J * BT + wn * WT;
+  const int ibase = I * BT + wm * C::WTM;
+  const int jbase = J * BT + wn * WTN;
 #pragma unroll
-  for (int a = 0; a < F; ++a) {
+  for (int a = 0; a < FM; ++a) {
 #pragma unroll
-    for (int b = 0; b < F; ++b)
+    for (int b = 0; b < FN; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sN[(4 * (lane >> 4) + r) * WT + b * 16 + (lane & 15)] = acc[a][b][r];
+      for (int r = 0; r < 4; ++r) sN[(4 * (lane >> 4) + r) * WTN + b * 16 + (lane & 15)] = acc[a][b][r];
     __builtin_amdgcn_wave_barrier();
     const int i0 = ibase + a * 16;
     for (int e = lane; e < STRIP; e += 64) {
-      const int rr = e / WT, cc = e % WT;
+      const int rr = e / WTN, cc = e % WTN;
       const int i = i0 + rr, j = jbase + cc;
       const int v11 = sN[e];
       const float v = mi_value(P.m, sColA[i - I * BT], sColB[j - J * BT], v11, P.epi, P.tau);
@@ -469,13 +414,14 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
         const int cc = e / 16, rr = e % 16;
         const int i = i0 + rr, j = jbase + cc;
         if (i < n && j < n) {
-          P.out[j * ln + i] = sM[rr * WT + cc];
-          if (P.n11_out) P.n11_out[j * ln + i] = sN[rr * WT + cc];
+          P.out[j * ln + i] = sM[rr * WTN + cc];
+          if (P.n11_out) P.n11_out[j * ln + i] = sN[rr * WTN + cc];
         }
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
+#endif
 }
 
 }  // namespace mi

@@ -22,26 +22,32 @@ const char* last_error();
 struct DeviceInfo {
   int device = 0;
   int cus = 0;
-  int occ[2] = {1, 1};   // plain kernel workgroups per CU, tile 128 / 256
-  int pocc[2] = {1, 1};  // persistent kernel workgroups per CU
+  int occ[kNumCfg] = {1, 1};   // plain kernel workgroups per CU, per configuration
+  int pocc[kNumCfg] = {1, 1};  // persistent kernel workgroups per CU
 };
 
 struct Plan {
+  int cfg = 0;      // 0: 128 x 128 tiles, 1: 256 x 256 tiles
   int bt = 128;
-  int ntp = 0;
-  int ntiles = 0;
-  int splits = 1;
-  int kchunk = 0;
+  int ntp = 0;      // column panels
+  int ntiles = 0;   // upper-triangular tiles
+  int splits = 1;   // K splits
+  int kchunk = 0;   // rows per split
+  int tpx = 0;      // tiles per XCD in the plain launch
 };
 
 mi_status device_info(DeviceInfo* out);
-mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out);
+mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out);  // zeroed split-K scratch
 size_t workspace_bytes(const Plan& pl);
-Plan make_plan(int64_t m, int64_t n, int bt, int splits);
+Plan make_plan(int64_t m, int64_t n, int cfg, int splits);
+const int32_t* tile_table(int ntp, hipError_t* err);
 mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out);
 mi_status check_problem(const mi_problem* p, int64_t* ldx_out);
 bool is_aligned(const uint8_t* X, int64_t ldx);
-ProbDev make_probdev(const mi_problem* p, int64_t ldx, const Plan& pl, void* ws);
+ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const Plan& pl, void* ws,
+                     const int32_t* tiles);
+mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out);
+int64_t packed_pitch(int64_t n);
 mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot);
 mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode);
 

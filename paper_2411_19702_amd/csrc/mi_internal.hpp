@@ -16,12 +16,19 @@ struct UnitRef {
   int32_t pad;
 };
 
-hipError_t launch_plain(int bt, const ProbDev& P, hipStream_t st);
-hipError_t launch_persistent(int bt, const ProbDev* probs, const UnitRef* units, int nunits, int* head, int grid,
+// Tile configurations: 0 = 128 x 128 (Cfg128), 1 = 256 x 256 (Cfg256).
+constexpr int kNumCfg = 2;
+int cfg_tile(int cfg);
+int cfg_threads(int cfg);
+
+hipError_t launch_plain(int cfg, const ProbDev& P, hipStream_t st);
+hipError_t launch_persistent(int cfg, const ProbDev* probs, const UnitRef* units, int nunits, int* head, int grid,
                              hipStream_t st);
 hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st);
+hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Y, int64_t ldy,
+                         hipStream_t st);
 hipError_t fill_i32(int* p, int v, int count, hipStream_t st);
-int occupancy(int bt);
-int persistent_occupancy(int bt);
+int occupancy(int cfg);
+int persistent_occupancy(int cfg);
 
 }  // namespace mi

@@ -4,34 +4,39 @@
 
 namespace mi {
 
-// One workgroup per (tile, split) unit; unit u = split * ntiles + tile so that
-// workgroups that run together share a K range (their panels overlap in L2).
-template <int BT, bool ALIGNED>
-__global__ __launch_bounds__(NTHREADS) void k_plain(ProbDev P) {
-  __shared__ __attribute__((aligned(16))) uint8_t smem[TileGeom<BT>::LDS_BYTES];
+// Plain launch: one workgroup per (tile, split) unit.  Workgroup u runs on XCD
+// u % 8; XCD x owns the tile ranks [x * tpx, (x + 1) * tpx) of the order table
+// (a compact block of the triangle, so its panels are shared in that XCD's L2),
+// and all XCDs sweep the K splits in the same order, so the rows being read at
+// any moment are shared through the last-level cache.
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_plain(ProbDev P) {
+  __shared__ __attribute__((aligned(16))) uint8_t smem[C::LDS_BYTES];
   const int u = blockIdx.x;
-  run_unit<BT, ALIGNED>(P, u % P.ntiles, u / P.ntiles, smem);
+  const int xcd = u & 7, local = u >> 3;
+  const int tpx = P.tiles_per_xcd;
+  const int s = local / tpx, r = local - s * tpx;
+  const int t = xcd * tpx + r;
+  if (t >= P.ntiles || s >= P.splits) return;  // uniform: padding units of the grid
+  run_unit<C>(P, t, s, smem);
 }
 
 // Persistent workgroups pull units of many datasets from a device queue.
-template <int BT>
-__global__ __launch_bounds__(NTHREADS) void k_persistent(const ProbDev* __restrict__ probs,
-                                                         const UnitRef* __restrict__ units, int nunits,
-                                                         int* __restrict__ head) {
-  __shared__ __attribute__((aligned(16))) uint8_t smem[TileGeom<BT>::LDS_BYTES];
+template <class C>
+__global__ __launch_bounds__(C::NT) void k_persistent(const ProbDev* __restrict__ probs,
+                                                      const UnitRef* __restrict__ units, int nunits,
+                                                      int* __restrict__ head) {
+  __shared__ __attribute__((aligned(16))) uint8_t smem[C::LDS_BYTES];
   __shared__ int s_u;
   for (;;) {
     if (threadIdx.x == 0) s_u = atomicAdd(head, 1);
     __syncthreads();
-    const int u = s_u;
+    const int u = __builtin_amdgcn_readfirstlane(s_u);  // uniform: scalar loads of the unit and its dataset
     __syncthreads();
     if (u >= nunits) break;  // uniform: every wave leaves together
     const UnitRef ur = units[u];
     const ProbDev P = probs[ur.prob];
-    if (P.aligned)
-      run_unit<BT, true>(P, ur.tile, ur.split, smem);
-    else
-      run_unit<BT, false>(P, ur.tile, ur.split, smem);
+    run_unit<C>(P, ur.tile, ur.split, smem);
     __syncthreads();
   }
 }
@@ -51,29 +56,45 @@ __global__ void k_validate(const uint8_t* __restrict__ X, int64_t m, int64_t n, 
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
-template <int BT>
-static hipError_t launch_plain_bt(const ProbDev& P, int units, hipStream_t st) {
-  if (P.aligned)
-    hipLaunchKernelGGL((k_plain<BT, true>), dim3(units), dim3(NTHREADS), 0, st, P);
-  else
-    hipLaunchKernelGGL((k_plain<BT, false>), dim3(units), dim3(NTHREADS), 0, st, P);
+// Y[r][c] = X[r][c] for c < n, 0 for n <= c < ldy: a 16-byte aligned copy with
+// pitch ldy (a multiple of 16) for layouts the DMA path cannot read directly.
+__global__ void k_repack(const uint8_t* __restrict__ X, int64_t m, int64_t n, int64_t ldx, uint8_t* __restrict__ Y,
+                         int64_t ldy) {
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    const uint8_t* src = X + row * ldx;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(Y + row * ldy);
+    for (int64_t w = threadIdx.x; w < ldy / 4; w += blockDim.x) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t c = 4 * w + b;
+        if (c < n) v |= (uint32_t)src[c] << (8 * b);
+      }
+      dst[w] = v;
+    }
+  }
+}
+
+template <class C>
+static hipError_t launch_plain_c(const ProbDev& P, hipStream_t st) {
+  const int64_t grid = 8LL * P.tiles_per_xcd * P.splits;
+  hipLaunchKernelGGL(k_plain<C>, dim3((unsigned)grid), dim3(C::NT), 0, st, P);
   return hipGetLastError();
 }
 
-hipError_t launch_plain(int bt, const ProbDev& P, hipStream_t st) {
-  const int units = P.ntiles * P.splits;
-  if (units <= 0) return hipSuccess;
-  return bt == 256 ? launch_plain_bt<256>(P, units, st) : launch_plain_bt<128>(P, units, st);
+hipError_t launch_plain(int cfg, const ProbDev& P, hipStream_t st) {
+  if (P.ntiles <= 0 || P.splits <= 0) return hipSuccess;
+  return cfg == 1 ? launch_plain_c<Cfg256>(P, st) : launch_plain_c<Cfg128>(P, st);
 }
 
-hipError_t launch_persistent(int bt, const ProbDev* probs, const UnitRef* units, int nunits, int* head, int grid,
+hipError_t launch_persistent(int cfg, const ProbDev* probs, const UnitRef* units, int nunits, int* head, int grid,
                              hipStream_t st) {
   if (nunits <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, head, 0, 1);
-  if (bt == 256)
-    hipLaunchKernelGGL(k_persistent<256>, dim3(grid), dim3(NTHREADS), 0, st, probs, units, nunits, head);
+  if (cfg == 1)
+    hipLaunchKernelGGL(k_persistent<Cfg256>, dim3(grid), dim3(Cfg256::NT), 0, st, probs, units, nunits, head);
   else
-    hipLaunchKernelGGL(k_persistent<128>, dim3(grid), dim3(NTHREADS), 0, st, probs, units, nunits, head);
+    hipLaunchKernelGGL(k_persistent<Cfg128>, dim3(grid), dim3(Cfg128::NT), 0, st, probs, units, nunits, head);
   return hipGetLastError();
 }
 
@@ -84,30 +105,35 @@ hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, 
   return hipGetLastError();
 }
 
+hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Y, int64_t ldy,
+                         hipStream_t st) {
+  const int64_t blocks = m < 8192 ? m : 8192;
+  hipLaunchKernelGGL(k_repack, dim3((unsigned)blocks), dim3(256), 0, st, X, m, n, ldx, Y, ldy);
+  return hipGetLastError();
+}
+
 hipError_t fill_i32(int* p, int v, int count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3((count + 255) / 256), dim3(256), 0, st, p, v, count);
   return hipGetLastError();
 }
 
-int occupancy(int bt) {
+int cfg_tile(int cfg) { return cfg == 1 ? Cfg256::BT : Cfg128::BT; }
+int cfg_threads(int cfg) { return cfg == 1 ? Cfg256::NT : Cfg128::NT; }
+
+int occupancy(int cfg) {
   int blocks = 0;
-  hipError_t e;
-  if (bt == 256)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<256, true>, NTHREADS, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<128, true>, NTHREADS, 0);
+  hipError_t e = cfg == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg256>, Cfg256::NT, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg128>, Cfg128::NT, 0);
   if (e != hipSuccess || blocks < 1) blocks = 1;
   return blocks;
 }
 
-int persistent_occupancy(int bt) {
+int persistent_occupancy(int cfg) {
   int blocks = 0;
-  hipError_t e;
-  if (bt == 256)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<256>, NTHREADS, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<128>, NTHREADS, 0);
+  hipError_t e = cfg == 1
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg256>, Cfg256::NT, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg128>, Cfg128::NT, 0);
   if (e != hipSuccess || blocks < 1) blocks = 1;
   return blocks;
 }
