@@ -100,6 +100,13 @@ def main() -> int:
     ap.add_argument("--epilogue", type=int, default=0, help="0 fp32, 1 fp32 + fp64 fallback, 2 fp64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for cpu_baseline (0: skip)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner for this shape first")
+    ap.add_argument("--pitch", type=int, default=0, help="row pitch of X in bytes (0: dense, pitch = n)")
+    ap.add_argument("--shape", default="", help="M,N: time a random M x N matrix instead of a named workload")
+    ap.add_argument("--tile", type=int, default=0, help="force a tile config (1: 128, 2: 256)")
+    ap.add_argument("--splits", type=int, default=0, help="force the K-split count")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark, run a plain device copy of MIB MiB per step "
+                         "(reference for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -114,18 +121,38 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 2
     dev = torch.device("cuda:0")
-    spec = getattr(synth, WORKLOADS[args.workload])()
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            torch.add(src, 0, out=dst)  # one elementwise kernel: reads nbytes, writes nbytes
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": args.warmup + args.steps}), flush=True)
+        return 0
+    if args.shape:
+        sm, sn = (int(v) for v in args.shape.split(","))
+        spec = synth.spec_random(7, sm, sn, 0.001, 0.2)
+        args.workload = f"random_{sm}x{sn}"
+    else:
+        spec = getattr(synth, WORKLOADS[args.workload])()
+    if args.pitch:
+        spec.ldx = args.pitch
     m, n = spec.m, spec.n
-    X = synth.generate(spec, device=dev)
+    X = synth.generate(spec, device=dev)[:, :n]
     out = torch.empty((n, n), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     if args.tune:
         mi.mi_tune(m, n, n)
-    tile, splits = mi.mi_plan(m, n, n)
+    tile, splits = mi.mi_plan(m, n, X.stride(0))
+    if args.tile:
+        tile = args.tile
+    if args.splits:
+        splits = args.splits
     stream = torch.cuda.current_stream()
 
     def step():
-        mi.mi_all_pairs_ex(X, out=out, epilogue=args.epilogue, stream=stream)
+        mi.mi_all_pairs_ex(X, out=out, epilogue=args.epilogue, tile=args.tile, splits=args.splits, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -160,7 +187,7 @@ def main() -> int:
         "dtype": "int8",
         "data": "synthetic",
         "config": {
-            "workload": args.workload, "m": m, "n": n, "layout": "uint8 0/1 row-major",
+            "workload": args.workload, "m": m, "n": n, "layout": "uint8 0/1 row-major, pitch %d" % X.stride(0),
             "density": "p_j log-uniform [0.001, 0.2]" if args.workload.startswith("large") else "see recipe",
             "epilogue": ["fp32", "fp32+fp64-fallback", "fp64"][args.epilogue],
             "tile": [None, 128, 256][tile], "splits": splits,
@@ -172,7 +199,7 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_INT8_OPS,
             "traffic": traffic,
-            "kernel": "mi::k_plain<128, true>",
+            "kernel": "mi::k_plain<mi::Cfg<%d, 2, %d, 4>>" % ((128, 2) if tile == 1 else (256, 4)),
             "kernel_ms": avg_kernel_s * 1e3,
         },
     }

@@ -10,7 +10,8 @@
 //      operand layout (each lane: 8 consecutive samples of one column);
 //   3. accumulates the 1-1 counts n11 = X_I^T X_J (the Gram product of
 //      Section 2 step 2 / Section 3, the only matrix product of the method)
-//      with v_mfma_i32_16x16x64_i8, exact in int32;
+//      with v_mfma_i32_32x32x32_i8, exact in int32 (on gfx950 this shape has
+//      twice the int8 throughput of v_mfma_i32_16x16x64_i8);
 //   4. accumulates the column sums c_I, c_J of its rows with v_dot4_u32_u8 on
 //      the operand registers (Section 2 step 3 / Section 3.1 "Term 2");
 //   5. with several K-splits, adds its partial counts into a per-tile int32
@@ -32,6 +33,7 @@ namespace mi {
 
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 #define MI_LDS __attribute__((address_space(3)))
 
 constexpr int KT = 64;  // samples per stage = one MFMA K step
@@ -43,18 +45,19 @@ struct Cfg {
   static constexpr int NWAVES = WGM * WGN;
   static constexpr int NT = 64 * NWAVES;
   static constexpr int WTM = BT / WGM, WTN = BT / WGN;  // wave tile
-  static constexpr int FM = WTM / 16, FN = WTN / 16;    // 16x16 fragments
+  static constexpr int FM = WTM / 32, FN = WTN / 32;    // 32x32 fragments
   static constexpr int PANEL = BT * KT;                 // bytes of one panel stage
   static constexpr int STAGE = 2 * PANEL;               // panel I then panel J
   static constexpr int REGIONS = STAGE / 1024;          // 1 KB DMA regions
   static constexpr int LOADS = REGIONS / NWAVES;        // DMA instructions per wave per stage
   static constexpr int ROWS_PER_REGION = 1024 / BT;
   static constexpr int SEGS = BT / 16;                  // 16-byte segments per row
-  static constexpr int STRIP = 16 * WTN;                // epilogue strip elements per wave
-  static constexpr int COL_OFF = NS * STAGE;            // column sums after the ring
-  static constexpr int LDS_BYTES = NS * STAGE + 2 * BT * 4 + 16;
+  static constexpr int STRIP = 32 * WTN;                // epilogue strip elements per wave
+  static constexpr int STRIP_BYTES = 2 * STRIP * 4;     // int32 counts + FP32 MI of a strip
+  static constexpr int WAVES_PER_SLOT = STAGE / STRIP_BYTES;
+  static_assert(NS == 4, "the K loop is unrolled over four ring slots");
   static_assert(REGIONS % NWAVES == 0, "DMA regions must split evenly over waves");
-  static_assert(NWAVES * 2 * STRIP * 4 <= NS * STAGE, "epilogue strips must fit in the ring");
+  static_assert(WAVES_PER_SLOT >= 1 && NWAVES <= NS * WAVES_PER_SLOT, "epilogue strips must fit in the ring");
 };
 using Cfg128 = Cfg<128, 2, 2, 4>;  // 4 waves of 64 x 64; 65 KB LDS, 2 workgroups per CU
 using Cfg256 = Cfg<256, 2, 4, 4>;  // 8 waves of 128 x 64; 130 KB LDS, 1 workgroup per CU
@@ -77,8 +80,8 @@ struct ProbDev {
   int32_t kchunk;       // rows per split, a multiple of KT
   int32_t epi;          // mi_epilogue
   float tau;
-  int32_t tiles_per_xcd;  // plain launch: tiles owned by each of the 8 XCDs
-  int32_t pad;
+  int32_t tiles_per_xcd;  // plain launch, map 0: tiles owned by each of the 8 XCDs
+  int32_t map;            // plain launch: 0 = tile blocks per XCD, 1 = K splits per XCD
 };
 
 // ---------------------------------------------------------------------------
@@ -136,52 +139,49 @@ __device__ __forceinline__ float mi_value(int m, int ci, int cj, int n11, int ep
 // ---------------------------------------------------------------------------
 // LDS layout of one staged panel: 64 rows (samples) of BT bytes, row-major as
 // in X, with the 16-byte segments of row r permuted by  seg' = seg ^ f(r).
-// A transposed operand read makes each 16-lane group fetch one segment from 8
-// rows (two lanes per segment); the two groups of a half-wave use rows
-// {g*16 .. g*16+7} and {(g+1)*16 .. +7}.  f spreads those 16 rows over all 64
-// banks; the DMA writes are contiguous 1 KB runs and conflict-free anyway.
+//
+// Operands of v_mfma_i32_32x32x32_i8: lane l holds 16 consecutive samples
+// (k = (l / 32) * 16 ..) of fragment column l % 32.  They are read with
+// ds_read_b64_tr_b8, which transposes within each group of 16 lanes: if the
+// even lanes of a group address 8 bytes (columns c..c+7) of 8 consecutive
+// rows and the odd lanes the next 8 columns of the same rows, output lane i of
+// the group receives column c + i of those 8 rows.  Lane group G = l / 16
+// therefore reads column segment s + (G & 1) at sample rows (G / 2) * 16 + 0..7
+// (and + 8 for the second half of its 16 samples).
+//
+// A half-wave (two groups) reads 8 rows x 2 adjacent segments {s, s + 1}
+// (s even); f makes those 16 segment reads land in 16 distinct 4-bank groups:
+//   BT = 256 (a row spans all 64 banks): f = 2 (r & 7);
+//   BT = 128 (two rows per 64 banks):    f = 2 ((r >> 1) & 3).
+// f(r + 8) = f(r) and f(r + 32) = f(r), so the other reads of a fragment are
+// at fixed offsets 8 BT, 32 BT, 40 BT from the first.  The DMA writes are
+// contiguous 1 KB runs and conflict-free whatever f is.
 // ---------------------------------------------------------------------------
 template <int BT>
 __device__ __forceinline__ int seg_swz(int row) {
-  if (BT == 256) return (row & 7) | (((row >> 4) & 1) << 3);     // 16 segments per row
-  return ((row >> 1) & 3) | (((row >> 4) & 1) << 2);             // 8 segments, 2 rows per bank row
+  if (BT == 256) return 2 * (row & 7);
+  return 2 * ((row >> 1) & 3);
 }
 
-// Byte offset (inside one panel) read by `lane` for the first half (samples
-// g*16 .. g*16+7) of the operand fragment whose 16 columns start at segment s;
-// the second half (samples +8) is 8 rows further, i.e. + 8 * BT bytes.
+// Byte offset (inside one panel) of this lane's first transposed read for the
+// 32-column fragment starting at (even) segment s: samples (G/2)*16 + 0..7.
 template <int BT>
 __device__ __forceinline__ int frag_off(int s, int lane) {
-  const int g = lane >> 4, j = lane & 15;
-  const int row = g * 16 + (j >> 1);
-  return row * BT + ((s ^ seg_swz<BT>(row)) << 4) + ((j & 1) << 3);
+  const int G = lane >> 4, j = lane & 15;
+  const int row = (G >> 1) * 16 + (j >> 1);
+  const int seg = s + (G & 1);
+  return row * BT + ((seg ^ seg_swz<BT>(row)) << 4) + ((j & 1) << 3);
 }
 
-// Read the fragments of one stage: NF fragments at LDS byte addresses
-// base + a[f] (plus 8 * BT for the second half).  The wait for the reads is
-// inside the same asm block, so every output is complete when the block ends.
-template <int BT, int NF>
-__device__ __forceinline__ void read_frags(v4i (&fr)[NF], const uint32_t (&a)[NF], uint32_t base) {
-  static_assert(NF % 4 == 0, "fragments are read four at a time");
-#pragma unroll
-  for (int f = 0; f < NF; f += 4) {
-    v2i x[8];
-    asm volatile(
-        "ds_read_b64_tr_b8 %0, %8\n\t"
-        "ds_read_b64_tr_b8 %1, %8 offset:%12\n\t"
-        "ds_read_b64_tr_b8 %2, %9\n\t"
-        "ds_read_b64_tr_b8 %3, %9 offset:%12\n\t"
-        "ds_read_b64_tr_b8 %4, %10\n\t"
-        "ds_read_b64_tr_b8 %5, %10 offset:%12\n\t"
-        "ds_read_b64_tr_b8 %6, %11\n\t"
-        "ds_read_b64_tr_b8 %7, %11 offset:%12\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]), "=&v"(x[7])
-        : "v"(base + a[f]), "v"(base + a[f + 1]), "v"(base + a[f + 2]), "v"(base + a[f + 3]), "i"(8 * BT)
-        : "memory");
-#pragma unroll
-    for (int q = 0; q < 4; ++q) fr[f + q] = v4i{x[2 * q].x, x[2 * q].y, x[2 * q + 1].x, x[2 * q + 1].y};
-  }
+// One operand fragment (32 columns x 16 samples per lane, one 32-sample K
+// step): two transposed 8-sample reads, 8 rows apart.  The compiler tracks
+// these reads (and, because every ring slot is its own LDS object, which DMA
+// writes they depend on), so it can issue them ahead of the MFMAs that use them.
+template <int BT>
+__device__ __forceinline__ v4i read_frag(const uint8_t* p) {
+  const v2i lo = __builtin_amdgcn_ds_read_tr8_b64_v2i32((MI_LDS v2i*)(p));
+  const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((MI_LDS v2i*)(p + 8 * BT));
+  return v4i{lo.x, lo.y, hi.x, hi.y};
 }
 
 __device__ __forceinline__ uint32_t dot_ones(const v4i& v, uint32_t acc) {
@@ -211,9 +211,18 @@ __device__ __forceinline__ void tile_ij(const ProbDev& P, int t, int& I, int& J)
   J = v & 0xFFFF;
 }
 
-// One work unit.  smem: C::LDS_BYTES bytes, 16-aligned.
+// LDS of one workgroup: the four ring slots are separate objects (so the
+// compiler can tell which DMA each operand read depends on), plus the column
+// sums and a flag.
 template <class C>
-__device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t* smem) {
+struct Smem {
+  uint8_t* slot[4];
+  int32_t* cols;  // 2 * BT + 4 int32
+};
+
+// One work unit.
+template <class C>
+__device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const Smem<C>& sm) {
 #if defined(__HIP_DEVICE_COMPILE__)  // device-only body (gfx950 builtins and asm)
   constexpr int BT = C::BT, FM = C::FM, FN = C::FN;
   const int tid = threadIdx.x;
@@ -228,7 +237,7 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
   const int k1 = min(P.m, k0 + P.kchunk);
   const int nsteps = (k1 - k0 + KT - 1) / KT;
 
-  int32_t* sColA = reinterpret_cast<int32_t*>(smem + C::COL_OFF);
+  int32_t* sColA = sm.cols;
   int32_t* sColB = sColA + BT;
   int32_t* sFlag = sColB + BT;
   for (int c = tid; c < 2 * BT; c += C::NT) sColA[c] = 0;
@@ -249,27 +258,27 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
     voff[i] = row * (int)P.ldx + col0 + 16 * seg;
     ldsoff[i] = (uint32_t)R * 1024u;
   }
-  const uint32_t lds_base = (uint32_t)(uintptr_t)(MI_LDS void*)smem;
-  auto dma_stage = [&](int ks, int buf) {
+  auto dma_stage = [&](int ks, uint8_t* slot) {
     const __amdgpu_buffer_rsrc_t rs = stage_rsrc(P, ks, k1);
 #pragma unroll
     for (int i = 0; i < C::LOADS; ++i)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rs, (MI_LDS void*)(uintptr_t)(lds_base + (uint32_t)buf * C::STAGE + ldsoff[i]), 16, voff[i], 0, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (MI_LDS void*)(slot + ldsoff[i]), 16, voff[i], 0, 0, 0);
   };
 
   // Operand read offsets (inside a stage) for this lane's fragments.
   uint32_t aoff[FM], boff[FN];
 #pragma unroll
-  for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off<BT>((wm * C::WTM) / 16 + a, lane);
+  for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off<BT>((wm * C::WTM) / 16 + 2 * a, lane);
 #pragma unroll
-  for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off<BT>((wn * C::WTN) / 16 + b, lane));
+  for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off<BT>((wn * C::WTN) / 16 + 2 * b, lane));
 
-  v4i acc[FM][FN];
+  v16i acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
   uint32_t csA[FM], csB[FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a) csA[a] = 0u;
@@ -277,46 +286,64 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
   for (int b = 0; b < FN; ++b) csB[b] = 0u;
   const bool sumA = (wn == 0), sumB = (wm == 0);
 
-  // Prologue: stages 0 .. NS-2 in flight.
-#pragma unroll
-  for (int st = 0; st < C::NS - 1; ++st) dma_stage(k0 + st * KT, st);
+  // Prologue: stages 0 .. 2 in flight, in slots 0 .. 2.
+  dma_stage(k0, sm.slot[0]);
+  dma_stage(k0 + KT, sm.slot[1]);
+  dma_stage(k0 + 2 * KT, sm.slot[2]);
 
-  for (int step = 0; step < nsteps; ++step) {
-    // This wave's DMA for stage `step` is done once at most (NS-2) stages of
-    // later loads are outstanding; the barrier then covers every wave, and
-    // also guarantees that all waves finished reading the buffer refilled next.
-    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"i"((C::NS - 2) * C::LOADS) : "memory");
-    dma_stage(k0 + (step + C::NS - 1) * KT, (step + C::NS - 1) % C::NS);
-    const uint32_t sb = lds_base + (uint32_t)(step % C::NS) * C::STAGE;
-    v4i fa[FM], fb[FN];
-    read_frags<BT, FM>(fa, aoff, sb);
-    read_frags<BT, FN>(fb, boff, sb);
-    if (sumA) {
+  // One step: stage `step` is in slot cur; stage step + 3 goes to slot nxt
+  // (the slot read in the previous step).
+  auto do_step = [&](int step, uint8_t* cur, uint8_t* nxt) {
+    // This wave's DMA for stage `step` is done once at most two stages of
+    // later loads are outstanding, and its reads of the previous step are
+    // done; the barrier extends both to every wave, so the slot refilled next
+    // is no longer being read and the current one is complete.
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"i"(2 * C::LOADS) : "memory");
+    dma_stage(k0 + (step + 3) * KT, nxt);
 #pragma unroll
-      for (int a = 0; a < FM; ++a) csA[a] = dot_ones(fa[a], csA[a]);
+    for (int kk = 0; kk < 2; ++kk) {
+      const uint8_t* kb = cur + kk * 32 * BT;
+      v4i fa[FM], fb[FN];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) fb[b] = read_frag<BT>(kb + boff[b]);
+#pragma unroll
+      for (int a = 0; a < FM; ++a) fa[a] = read_frag<BT>(kb + aoff[a]);
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+      if (sumA) {
+#pragma unroll
+        for (int a = 0; a < FM; ++a) csA[a] = dot_ones(fa[a], csA[a]);
+      }
+      if (sumB) {
+#pragma unroll
+        for (int b = 0; b < FN; ++b) csB[b] = dot_ones(fb[b], csB[b]);
+      }
     }
-    if (sumB) {
-#pragma unroll
-      for (int b = 0; b < FN; ++b) csB[b] = dot_ones(fb[b], csB[b]);
-    }
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-      for (int b = 0; b < FN; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  };
+
+  // Unrolled over the four slots; a unit whose step count is not a multiple
+  // of four runs up to three extra steps on zeros (rows past k1 read as zero).
+  for (int step = 0; step < nsteps; step += 4) {
+    do_step(step, sm.slot[0], sm.slot[3]);
+    do_step(step + 1, sm.slot[1], sm.slot[0]);
+    do_step(step + 2, sm.slot[2], sm.slot[1]);
+    do_step(step + 3, sm.slot[3], sm.slot[2]);
   }
   // Drain the DMA of stages past the end before the ring is reused.
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
 
-  // Column sums of this unit's rows: the four lane groups of a wave hold
-  // partial sums of the same 16 columns; combine them in LDS.
+  // Column sums of this unit's rows: lanes l and l + 32 hold partial sums of
+  // the same fragment column; combine them in LDS.
   if (sumA) {
 #pragma unroll
-    for (int a = 0; a < FM; ++a) atomicAdd(&sColA[wm * C::WTM + a * 16 + (lane & 15)], (int)csA[a]);
+    for (int a = 0; a < FM; ++a) atomicAdd(&sColA[wm * C::WTM + a * 32 + (lane & 31)], (int)csA[a]);
   }
   if (sumB) {
 #pragma unroll
-    for (int b = 0; b < FN; ++b) atomicAdd(&sColB[wn * C::WTN + b * 16 + (lane & 15)], (int)csB[b]);
+    for (int b = 0; b < FN; ++b) atomicAdd(&sColB[wn * C::WTN + b * 32 + (lane & 31)], (int)csB[b]);
   }
   __syncthreads();
 
@@ -329,9 +356,9 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = wm * C::WTM + a * 16 + 4 * (lane >> 4) + r;
-          const int col = wn * C::WTN + b * 16 + (lane & 15);
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm * C::WTM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int col = wn * C::WTN + b * 32 + (lane & 31);
           const int v = acc[a][b][r];
           if (v) __hip_atomic_fetch_add(&wsn[row * BT + col], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -354,9 +381,9 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = wm * C::WTM + a * 16 + 4 * (lane >> 4) + r;
-          const int col = wn * C::WTN + b * 16 + (lane & 15);
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm * C::WTM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int col = wn * C::WTN + b * 32 + (lane & 31);
           int32_t* w = &wsn[row * BT + col];
           acc[a][b][r] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(w, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -371,7 +398,7 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
   }
 
   // Epilogue: derived cells, MI, tile and mirror write-back.  Each wave moves
-  // its accumulators through LDS (the ring is free now) one 16-row strip at a
+  // its accumulators through LDS (the ring is free now) one 32-row strip at a
   // time: pass 1 reads the strip row-wise, evaluates MI once per element and
   // writes the tile rows (consecutive lanes, consecutive j); pass 2 reads the
   // strip column-wise and writes the mirror rows (consecutive i).
@@ -385,7 +412,9 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
   }
   constexpr int WTN = C::WTN;
   constexpr int STRIP = C::STRIP;
-  int32_t* sN = reinterpret_cast<int32_t*>(smem) + wave * 2 * STRIP;
+  const int ws = wave / C::WAVES_PER_SLOT;  // selects, not an indexed array (keeps it out of memory)
+  uint8_t* strip_slot = ws == 0 ? sm.slot[0] : (ws == 1 ? sm.slot[1] : (ws == 2 ? sm.slot[2] : sm.slot[3]));
+  int32_t* sN = reinterpret_cast<int32_t*>(strip_slot + (wave % C::WAVES_PER_SLOT) * C::STRIP_BYTES);
   float* sM = reinterpret_cast<float*>(sN + STRIP);
   const int ibase = I * BT + wm * C::WTM;
   const int jbase = J * BT + wn * WTN;
@@ -394,9 +423,10 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
 #pragma unroll
     for (int b = 0; b < FN; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sN[(4 * (lane >> 4) + r) * WTN + b * 16 + (lane & 15)] = acc[a][b][r];
+      for (int r = 0; r < 16; ++r)
+        sN[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * WTN + b * 32 + (lane & 31)] = acc[a][b][r];
     __builtin_amdgcn_wave_barrier();
-    const int i0 = ibase + a * 16;
+    const int i0 = ibase + a * 32;
     for (int e = lane; e < STRIP; e += 64) {
       const int rr = e / WTN, cc = e % WTN;
       const int i = i0 + rr, j = jbase + cc;
@@ -411,7 +441,7 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, uint8_t
     __builtin_amdgcn_wave_barrier();
     if (!diag) {
       for (int e = lane; e < STRIP; e += 64) {
-        const int cc = e / 16, rr = e % 16;
+        const int cc = e / 32, rr = e % 32;
         const int i = i0 + rr, j = jbase + cc;
         if (i < n && j < n) {
           P.out[j * ln + i] = sM[rr * WTN + cc];

@@ -33,7 +33,8 @@ struct Plan {
   int ntiles = 0;   // upper-triangular tiles
   int splits = 1;   // K splits
   int kchunk = 0;   // rows per split
-  int tpx = 0;      // tiles per XCD in the plain launch
+  int tpx = 0;      // tiles per XCD in the plain launch (map 0)
+  int map = 0;      // plain-launch unit-to-XCD mapping (0 tile blocks, 1 K splits)
 };
 
 mi_status device_info(DeviceInfo* out);
