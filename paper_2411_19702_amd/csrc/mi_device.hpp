@@ -12,8 +12,9 @@
 //      Section 2 step 2 / Section 3, the only matrix product of the method)
 //      with v_mfma_i32_32x32x32_i8, exact in int32 (on gfx950 this shape has
 //      twice the int8 throughput of v_mfma_i32_16x16x64_i8);
-//   4. accumulates the column sums c_I, c_J of its rows with v_dot4_u32_u8 on
-//      the operand registers (Section 2 step 3 / Section 3.1 "Term 2");
+//   4. accumulates the column sums c_I, c_J of its rows from the operand
+//      registers with bytewise adds folded by v_dot4_u32_u8 (Section 2 step 3
+//      / Section 3.1 "Term 2");
 //   5. with several K-splits, adds its partial counts into a per-tile int32
 //      workspace; the last unit to arrive at a tile reads the totals back,
 //      clears the workspace, and alone runs the epilogue;
@@ -184,14 +185,6 @@ __device__ __forceinline__ v4i read_frag(const uint8_t* p) {
   return v4i{lo.x, lo.y, hi.x, hi.y};
 }
 
-__device__ __forceinline__ uint32_t dot_ones(const v4i& v, uint32_t acc) {
-  acc = __builtin_amdgcn_udot4((uint32_t)v.x, 0x01010101u, acc, false);
-  acc = __builtin_amdgcn_udot4((uint32_t)v.y, 0x01010101u, acc, false);
-  acc = __builtin_amdgcn_udot4((uint32_t)v.z, 0x01010101u, acc, false);
-  acc = __builtin_amdgcn_udot4((uint32_t)v.w, 0x01010101u, acc, false);
-  return acc;
-}
-
 __device__ __forceinline__ uint32_t sgpr(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Buffer descriptor for the rows [ks, min(ks + KT, kend)) of X: reads at byte
@@ -279,72 +272,90 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
     for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
-  uint32_t csA[FM], csB[FN];
-#pragma unroll
-  for (int a = 0; a < FM; ++a) csA[a] = 0u;
-#pragma unroll
-  for (int b = 0; b < FN; ++b) csB[b] = 0u;
-  const bool sumA = (wn == 0), sumB = (wm == 0);
+  // Column sums: every wave sums one of its A fragments (index wn) and one of
+  // its B fragments (index wm), so each column of both panels is summed by
+  // exactly one wave and the work is the same for all waves.  Bytes are 0/1:
+  // the four dwords of a fragment half add bytewise without carries (<= 4 per
+  // byte), accumulate bytewise for four steps (<= 32 per byte), and are folded
+  // into 32-bit totals with v_dot4 once per four steps.
+  static_assert(FM == C::WGN && FN == C::WGM, "one summed fragment per wave and panel");
+  uint32_t pkA = 0u, pkB = 0u, csA = 0u, csB = 0u;
 
-  // Prologue: stages 0 .. 2 in flight, in slots 0 .. 2.
+  // Fragments are read one K half ahead of their MFMAs (two register sets):
+  // while the MFMAs of one half execute, the wave reads the next half, and
+  // the barrier that publishes the next stage sits between the two halves,
+  // so matrix work is queued while the wave waits at it.
+  v4i fa0[FM], fb0[FN], fa1[FM], fb1[FN];
+  auto read_half = [&](const uint8_t* slot, int kk, v4i (&fa)[FM], v4i (&fb)[FN]) {
+    const uint8_t* kb = slot + kk * 32 * BT;
+#pragma unroll
+    for (int b = 0; b < FN; ++b) fb[b] = read_frag<BT>(kb + boff[b]);
+#pragma unroll
+    for (int a = 0; a < FM; ++a) fa[a] = read_frag<BT>(kb + aoff[a]);
+  };
+  auto mma_half = [&](const v4i (&fa)[FM], const v4i (&fb)[FN]) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+      if (a == wn) pkA += ((uint32_t)fa[a].x + (uint32_t)fa[a].y) + ((uint32_t)fa[a].z + (uint32_t)fa[a].w);
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+      if (b == wm) pkB += ((uint32_t)fb[b].x + (uint32_t)fb[b].y) + ((uint32_t)fb[b].z + (uint32_t)fb[b].w);
+  };
+  // Stage `step + 1` complete for every wave, and every wave done reading the
+  // slot that the next DMA refills: this wave waits for its own DMA of that
+  // stage (at most two later stages outstanding) and its own LDS reads, then
+  // the barrier extends both to the workgroup.
+  auto stage_barrier = [&]() {
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"i"(2 * C::LOADS) : "memory");
+  };
+
+  // Prologue: stages 0 .. 2 in flight in slots 0 .. 2; once stage 0 is in,
+  // stage 3 goes to slot 3 and the first half of stage 0 is read.
   dma_stage(k0, sm.slot[0]);
   dma_stage(k0 + KT, sm.slot[1]);
   dma_stage(k0 + 2 * KT, sm.slot[2]);
+  stage_barrier();
+  dma_stage(k0 + 3 * KT, sm.slot[3]);
+  read_half(sm.slot[0], 0, fa0, fb0);
 
-  // One step: stage `step` is in slot cur; stage step + 3 goes to slot nxt
-  // (the slot read in the previous step).
+  // Step `step` (stage in slot cur, the next stage in slot nxt).
   auto do_step = [&](int step, uint8_t* cur, uint8_t* nxt) {
-    // This wave's DMA for stage `step` is done once at most two stages of
-    // later loads are outstanding, and its reads of the previous step are
-    // done; the barrier extends both to every wave, so the slot refilled next
-    // is no longer being read and the current one is complete.
-    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"i"(2 * C::LOADS) : "memory");
-    dma_stage(k0 + (step + 3) * KT, nxt);
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const uint8_t* kb = cur + kk * 32 * BT;
-      v4i fa[FM], fb[FN];
-#pragma unroll
-      for (int b = 0; b < FN; ++b) fb[b] = read_frag<BT>(kb + boff[b]);
-#pragma unroll
-      for (int a = 0; a < FM; ++a) fa[a] = read_frag<BT>(kb + aoff[a]);
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
-      if (sumA) {
-#pragma unroll
-        for (int a = 0; a < FM; ++a) csA[a] = dot_ones(fa[a], csA[a]);
-      }
-      if (sumB) {
-#pragma unroll
-        for (int b = 0; b < FN; ++b) csB[b] = dot_ones(fb[b], csB[b]);
-      }
-    }
+    read_half(cur, 1, fa1, fb1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_half(fa0, fb0);
+    __builtin_amdgcn_sched_barrier(0);
+    stage_barrier();
+    dma_stage(k0 + (step + 4) * KT, cur);  // stage step + 4 into the slot just consumed
+    read_half(nxt, 0, fa0, fb0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_half(fa1, fb1);
+    __builtin_amdgcn_sched_barrier(0);
   };
 
   // Unrolled over the four slots; a unit whose step count is not a multiple
   // of four runs up to three extra steps on zeros (rows past k1 read as zero).
   for (int step = 0; step < nsteps; step += 4) {
-    do_step(step, sm.slot[0], sm.slot[3]);
-    do_step(step + 1, sm.slot[1], sm.slot[0]);
-    do_step(step + 2, sm.slot[2], sm.slot[1]);
-    do_step(step + 3, sm.slot[3], sm.slot[2]);
+    do_step(step, sm.slot[0], sm.slot[1]);
+    do_step(step + 1, sm.slot[1], sm.slot[2]);
+    do_step(step + 2, sm.slot[2], sm.slot[3]);
+    do_step(step + 3, sm.slot[3], sm.slot[0]);
+    csA = __builtin_amdgcn_udot4(pkA, 0x01010101u, csA, false);
+    csB = __builtin_amdgcn_udot4(pkB, 0x01010101u, csB, false);
+    pkA = 0u;
+    pkB = 0u;
   }
   // Drain the DMA of stages past the end before the ring is reused.
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
 
   // Column sums of this unit's rows: lanes l and l + 32 hold partial sums of
   // the same fragment column; combine them in LDS.
-  if (sumA) {
-#pragma unroll
-    for (int a = 0; a < FM; ++a) atomicAdd(&sColA[wm * C::WTM + a * 32 + (lane & 31)], (int)csA[a]);
-  }
-  if (sumB) {
-#pragma unroll
-    for (int b = 0; b < FN; ++b) atomicAdd(&sColB[wn * C::WTN + b * 32 + (lane & 31)], (int)csB[b]);
-  }
+  atomicAdd(&sColA[wm * C::WTM + wn * 32 + (lane & 31)], (int)csA);
+  atomicAdd(&sColB[wn * C::WTN + wm * 32 + (lane & 31)], (int)csB);
   __syncthreads();
 
   // Split-K: publish partials; the last unit of the tile takes over.
