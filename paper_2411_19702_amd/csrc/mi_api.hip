@@ -109,7 +109,7 @@ mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out) 
 
 mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out) { return scratch(st, 0, slot, bytes, out); }
 
-static void release_scratch_of(hipStream_t st) {
+void release_scratch_of(hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   for (auto it = g_ws.begin(); it != g_ws.end();) {
     if (it->first.st == st) {
@@ -389,6 +389,8 @@ struct GraphEntry {
 };
 static std::mutex g_graph_mu;
 static std::map<std::string, GraphEntry> g_graphs;
+static std::map<int, hipStream_t> g_capture_stream;
+static std::mutex g_capture_mu;
 
 static std::string batch_key(const mi_problem* probs, int64_t count, const std::vector<Plan>& plans, hipStream_t st) {
   std::string k;
@@ -506,7 +508,11 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   }
 
   if (mode == MI_BATCH_GRAPH) {
-    const std::string key = batch_key(probs, count, plans, st);
+    // The captured launches bake in the workspace and repack addresses, so
+    // they are part of the cache key: a reallocated buffer means a new graph.
+    char extra[96];
+    snprintf(extra, sizeof extra, "|ws=%p|rp=%p", ws, rp);
+    const std::string key = batch_key(probs, count, plans, st) + extra;
     hipGraphExec_t exec = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -514,18 +520,32 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
       if (it != g_graphs.end()) exec = it->second.exec;
     }
     if (!exec) {
+      // Capture on a private stream (the caller's may be the legacy default
+      // stream, which cannot be captured); the graph is launched on st.
+      hipStream_t cap = nullptr;
+      {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        hipStream_t& c = g_capture_stream[di.device];
+        if (!c) HIPCHK(hipStreamCreateWithFlags(&c, hipStreamNonBlocking));
+        cap = c;
+      }
+      std::lock_guard<std::mutex> cap_lk(g_capture_mu);  // one capture at a time on that stream
       hipGraph_t graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      hipError_t e = repack_all();
-      for (int64_t d = 0; d < count && e == hipSuccess; ++d)
-        if (probs[d].n > 0) e = launch_plain(plans[d].cfg, P[d], st);
+      HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int64_t d = 0; d < count && e == hipSuccess; ++d) {
+        if (probs[d].n == 0) continue;
+        if (!aligned[d])
+          e = launch_repack(probs[d].X, probs[d].m, probs[d].n, ldx[d], (uint8_t*)P[d].X, P[d].ldx, cap);
+        if (e == hipSuccess) e = launch_plain(plans[d].cfg, P[d], cap);
+      }
       if (e != hipSuccess) {
         hipGraph_t g2 = nullptr;
-        (void)hipStreamEndCapture(st, &g2);
+        (void)hipStreamEndCapture(cap, &g2);
         if (g2) (void)hipGraphDestroy(g2);
         return fail(MI_ERR_DEVICE, "launch during capture: %s", hipGetErrorString(e));
       }
-      HIPCHK(hipStreamEndCapture(st, &graph));
+      HIPCHK(hipStreamEndCapture(cap, &graph));
       e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(MI_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
@@ -604,6 +624,24 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     dU += units[c].size();
   }
   return MI_OK;
+}
+
+void release_stream_resources(hipStream_t st) {
+  release_scratch_of(st);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (auto it = g_batch.begin(); it != g_batch.end();) {
+    if (it->first.second == st) {
+      if (it->second.copied) {
+        (void)hipEventSynchronize(it->second.copied);
+        (void)hipEventDestroy(it->second.copied);
+      }
+      if (it->second.host) (void)hipHostFree(it->second.host);
+      if (it->second.dev) (void)hipFree(it->second.dev);
+      it = g_batch.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 // ------------------------------------------------------------------- tuner --

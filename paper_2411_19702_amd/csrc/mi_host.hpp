@@ -50,6 +50,8 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
 mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out);
 int64_t packed_pitch(int64_t n);
 mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot);
+void release_scratch_of(hipStream_t st);
+void release_stream_resources(hipStream_t st);  // scratch and batch descriptors of a stream
 mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode);
 
 }  // namespace mi

@@ -1,0 +1,313 @@
+// mi_server.cpp -- continuous-batching request loop (include/mi_server.h).
+//
+// One host thread per server.  Requests wait in a FIFO; whenever a slot (a
+// HIP stream) is free the loop admits every waiting request, in order, that
+// fits the HBM budget next to what is already running, and launches them
+// together (one persistent batched launch, or a plain launch for a single
+// request) on that slot.  Batches on different slots run concurrently on the
+// device.  Completion is detected by polling one event per batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mi.h"
+#include "mi_host.hpp"
+#include "mi_server.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum ReqState { kWaiting = 0, kRunning = 1, kDone = 2 };
+
+struct Req {
+  mi_problem p;
+  size_t bytes = 0;
+  Clock::time_point t_submit, t_done;
+  int state = kWaiting;
+  mi_status status = MI_OK;
+};
+
+struct Batch {
+  std::vector<uint64_t> tickets;
+  hipEvent_t ev = nullptr;
+  int slot = -1;
+  size_t bytes = 0;
+};
+
+constexpr int kMaxBatch = 256;  // requests launched together at most
+
+}  // namespace
+
+struct mi_server {
+  int dev = 0;
+  size_t budget = 0;
+  int nslots = 0;
+  size_t max_queue = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<char> slot_busy;
+  std::vector<hipEvent_t> free_events;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> waiting;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::vector<Batch> running;
+  size_t in_flight = 0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  mi_server_stats stats{};
+  std::thread th;
+
+  void loop();
+  void finish_batch(Batch& b, mi_status st, Clock::time_point now);
+};
+
+namespace {
+
+// Device memory a request holds while it is admitted.
+size_t request_bytes(const mi_problem& p, int64_t ldx) {
+  size_t b = (size_t)p.m * (size_t)ldx + (size_t)p.n * (size_t)p.n * sizeof(float);
+  if (p.n11_out) b += (size_t)p.n * (size_t)p.n * sizeof(int32_t);
+  if (p.colsum_out) b += (size_t)p.n * sizeof(int32_t);
+  if (p.n > 0) {
+    const int cfg = p.tile == MI_TILE_256 ? 1 : 0;
+    mi::Plan pl = mi::make_plan(p.m, p.n, p.tile == 0 ? (p.n >= 1536 ? 1 : 0) : cfg, 2);
+    b += mi::workspace_bytes(pl);  // independent of the split count
+    if (!mi::is_aligned(p.X, ldx)) b += (size_t)p.m * (size_t)mi::packed_pitch(p.n);
+  }
+  return b;
+}
+
+double seconds(Clock::duration d) { return std::chrono::duration<double>(d).count(); }
+
+}  // namespace
+
+void mi_server::finish_batch(Batch& b, mi_status st, Clock::time_point now) {
+  for (uint64_t t : b.tickets) {
+    auto it = reqs.find(t);
+    if (it == reqs.end()) continue;
+    it->second.state = kDone;
+    it->second.status = st;
+    it->second.t_done = now;
+    stats.completed++;
+  }
+  in_flight -= b.bytes;
+  stats.bytes_in_flight = in_flight;
+  slot_busy[b.slot] = 0;
+  if (b.ev) free_events.push_back(b.ev);
+  b.ev = nullptr;
+}
+
+void mi_server::loop() {
+  (void)hipSetDevice(dev);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    bool progressed = false;
+    // 1. Completed batches.
+    const auto now = Clock::now();
+    for (size_t i = 0; i < running.size();) {
+      hipError_t e = hipEventQuery(running[i].ev);
+      if (e == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      finish_batch(running[i], e == hipSuccess ? MI_OK : MI_ERR_DEVICE, now);
+      running.erase(running.begin() + i);
+      progressed = true;
+    }
+    if (progressed) cv_done.notify_all();
+
+    // 2. Admission: everything at the head of the queue that fits, onto one free slot.
+    int slot = -1;
+    for (int s = 0; s < nslots; ++s)
+      if (!slot_busy[s]) {
+        slot = s;
+        break;
+      }
+    if (slot >= 0 && !waiting.empty()) {
+      Batch b;
+      b.slot = slot;
+      std::vector<mi_problem> probs;
+      while (!waiting.empty() && (int)probs.size() < kMaxBatch) {
+        Req& r = reqs[waiting.front()];
+        if (in_flight + b.bytes + r.bytes > budget) break;  // first come, first served
+        b.bytes += r.bytes;
+        b.tickets.push_back(waiting.front());
+        probs.push_back(r.p);
+        r.state = kRunning;
+        waiting.pop_front();
+      }
+      if (!probs.empty()) {
+        slot_busy[slot] = 1;
+        in_flight += b.bytes;
+        stats.bytes_in_flight = in_flight;
+        stats.max_bytes_in_flight = std::max(stats.max_bytes_in_flight, in_flight);
+        size_t nrun = 0;
+        for (auto& rb : running) nrun += rb.tickets.size();
+        stats.max_in_flight = std::max<uint64_t>(stats.max_in_flight, nrun + probs.size());
+        stats.batches++;
+        if (free_events.empty()) {
+          hipEvent_t ev = nullptr;
+          if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) free_events.push_back(ev);
+        }
+        hipStream_t st = streams[slot];
+        lk.unlock();  // launches may allocate; clients can keep submitting
+        mi_status rc = probs.size() == 1 ? mi::run_one(&probs[0], st, 0)
+                                         : mi::run_batched(probs.data(), (int64_t)probs.size(), st, MI_BATCH_PERSISTENT);
+        lk.lock();
+        if (rc == MI_OK && !free_events.empty()) {
+          b.ev = free_events.back();
+          free_events.pop_back();
+          if (hipEventRecord(b.ev, st) != hipSuccess) rc = MI_ERR_DEVICE;
+        } else if (rc == MI_OK) {
+          rc = MI_ERR_DEVICE;
+        }
+        if (rc == MI_OK) {
+          running.push_back(b);
+        } else {
+          (void)hipStreamSynchronize(st);
+          finish_batch(b, rc, Clock::now());
+          cv_done.notify_all();
+        }
+        progressed = true;
+      }
+    }
+
+    if (stop && waiting.empty() && running.empty()) break;
+    if (!progressed) {
+      if (running.empty())
+        cv_work.wait_for(lk, std::chrono::milliseconds(2));
+      else
+        cv_work.wait_for(lk, std::chrono::microseconds(20));
+    }
+  }
+}
+
+extern "C" {
+
+mi_status mi_server_create(mi_server** server, size_t hbm_budget_bytes, int32_t max_slots, int32_t max_queue) {
+  mi::clear_error();
+  if (!server) return mi::fail(MI_ERR_INVALID_ARG, "server is NULL");
+  *server = nullptr;
+  if (hbm_budget_bytes == 0) return mi::fail(MI_ERR_INVALID_ARG, "budget must be > 0");
+  if (max_slots < 1 || max_slots > 64) return mi::fail(MI_ERR_INVALID_ARG, "max_slots must be in 1..64");
+  if (max_queue < 0) return mi::fail(MI_ERR_INVALID_ARG, "max_queue must be >= 0");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  mi_server* s = new mi_server();
+  s->dev = dev;
+  s->budget = hbm_budget_bytes;
+  s->nslots = max_slots;
+  s->max_queue = max_queue == 0 ? 65536 : (size_t)max_queue;
+  s->slot_busy.assign(max_slots, 0);
+  for (int i = 0; i < max_slots; ++i) {
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (auto x : s->streams) (void)hipStreamDestroy(x);
+      delete s;
+      return mi::fail(MI_ERR_DEVICE, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+    }
+    s->streams.push_back(st);
+  }
+  s->th = std::thread([s] { s->loop(); });
+  *server = s;
+  return MI_OK;
+}
+
+mi_status mi_server_submit(mi_server* s, const mi_problem* p, uint64_t* ticket) {
+  mi::clear_error();
+  if (!s || !ticket) return mi::fail(MI_ERR_INVALID_ARG, "server and ticket must be non-NULL");
+  int64_t ldx = 0;
+  mi_status st = mi::check_problem(p, &ldx);
+  if (st != MI_OK) return st;
+  if (p->validate) return mi::fail(MI_ERR_INVALID_ARG, "validate is not supported by the server");
+  Req r;
+  r.p = *p;
+  r.bytes = request_bytes(*p, ldx);
+  r.t_submit = Clock::now();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (r.bytes > s->budget) {
+    s->stats.rejected++;
+    return mi::fail(MI_ERR_BUDGET, "request needs %zu bytes, budget is %zu", r.bytes, s->budget);
+  }
+  if (s->waiting.size() >= s->max_queue) {
+    s->stats.rejected++;
+    return mi::fail(MI_ERR_QUEUE_FULL, "queue holds %zu waiting requests", s->waiting.size());
+  }
+  if (s->stop) return mi::fail(MI_ERR_INVALID_ARG, "server is shutting down");
+  const uint64_t t = s->next_ticket++;
+  s->reqs.emplace(t, r);
+  s->waiting.push_back(t);
+  s->stats.submitted++;
+  *ticket = t;
+  s->cv_work.notify_one();
+  return MI_OK;
+}
+
+mi_status mi_server_poll(mi_server* s, uint64_t ticket) {
+  mi::clear_error();
+  if (!s) return mi::fail(MI_ERR_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return mi::fail(MI_ERR_UNKNOWN_TICKET, "unknown ticket %llu", (unsigned long long)ticket);
+  return it->second.state == kDone ? MI_OK : MI_ERR_NOT_READY;
+}
+
+mi_status mi_server_wait(mi_server* s, uint64_t ticket, double timeout_s, double* latency_s) {
+  mi::clear_error();
+  if (!s) return mi::fail(MI_ERR_INVALID_ARG, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return mi::fail(MI_ERR_UNKNOWN_TICKET, "unknown ticket %llu", (unsigned long long)ticket);
+  const auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(
+                                           timeout_s > 0 ? timeout_s : 1e9));
+  while (it->second.state != kDone) {
+    if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout && it->second.state != kDone)
+      return mi::fail(MI_ERR_TIMEOUT, "ticket %llu not finished", (unsigned long long)ticket);
+    it = s->reqs.find(ticket);
+  }
+  const Req r = it->second;
+  s->reqs.erase(it);
+  if (latency_s) *latency_s = seconds(r.t_done - r.t_submit);
+  if (r.status != MI_OK) return mi::fail(r.status, "request %llu failed on the device", (unsigned long long)ticket);
+  return MI_OK;
+}
+
+mi_status mi_server_get_stats(mi_server* s, mi_server_stats* out) {
+  mi::clear_error();
+  if (!s || !out) return mi::fail(MI_ERR_INVALID_ARG, "server and stats must be non-NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  return MI_OK;
+}
+
+mi_status mi_server_destroy(mi_server* s) {
+  mi::clear_error();
+  if (!s) return mi::fail(MI_ERR_INVALID_ARG, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->th.joinable()) s->th.join();
+  for (auto st : s->streams) {
+    (void)hipStreamSynchronize(st);
+    mi::release_stream_resources(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (auto ev : s->free_events) (void)hipEventDestroy(ev);
+  delete s;
+  return MI_OK;
+}
+
+}  // extern "C"

@@ -54,6 +54,14 @@ class mi_problem(ctypes.Structure):
     ]
 
 
+class mi_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64), ("max_in_flight", ctypes.c_uint64),
+        ("max_bytes_in_flight", ctypes.c_size_t), ("bytes_in_flight", ctypes.c_size_t),
+    ]
+
+
 _lib = None
 
 
@@ -79,6 +87,12 @@ def lib() -> ctypes.CDLL:
         "mi_tuner_load": (i32, [ctypes.c_char_p]),
         "mi_tuner_clear": (None, []),
         "mi_last_error": (ctypes.c_char_p, []),
+        "mi_server_create": (i32, [P(vp), ctypes.c_size_t, i32, i32]),
+        "mi_server_submit": (i32, [vp, P(mi_problem), P(ctypes.c_uint64)]),
+        "mi_server_poll": (i32, [vp, ctypes.c_uint64]),
+        "mi_server_wait": (i32, [vp, ctypes.c_uint64, ctypes.c_double, P(ctypes.c_double)]),
+        "mi_server_get_stats": (i32, [vp, P(mi_server_stats)]),
+        "mi_server_destroy": (i32, [vp]),
         "mi_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -208,3 +222,52 @@ def mi_last_error() -> str:
 
 def mi_version() -> str:
     return lib().mi_version().decode()
+
+
+class Server:
+    """Continuous-batching request loop (include/mi_server.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, max_queue: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().mi_server_create(ctypes.byref(h), int(hbm_budget_bytes), int(max_slots), int(max_queue)))
+        self._h = h
+        self._keep = {}  # ticket -> tensors the request reads or writes (kept alive until collected)
+
+    def submit(self, X: torch.Tensor, out: torch.Tensor, keep=(), **kw) -> int:
+        p = make_problem(X, out, **kw)
+        t = ctypes.c_uint64()
+        _check(lib().mi_server_submit(self._h, ctypes.byref(p), ctypes.byref(t)))
+        self._keep[t.value] = (X, out) + tuple(keep)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        st = lib().mi_server_poll(self._h, ticket)
+        if st == 6:
+            return False
+        _check(st)
+        return True
+
+    def wait(self, ticket: int, timeout_s: float = 0.0) -> float:
+        lat = ctypes.c_double()
+        st = lib().mi_server_wait(self._h, ticket, float(timeout_s), ctypes.byref(lat))
+        if st != 8:  # a timeout leaves the ticket pending
+            self._keep.pop(ticket, None)
+        _check(st)
+        return lat.value
+
+    def stats(self) -> dict:
+        s = mi_server_stats()
+        _check(lib().mi_server_get_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in s._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().mi_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

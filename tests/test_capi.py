@@ -32,7 +32,7 @@ def declared_functions():
 def test_headers_declare_the_boundary():
     names = declared_functions()
     for required in ("mi_all_pairs", "mi_all_pairs_async", "mi_all_pairs_ex", "mi_all_pairs_batched",
-                     "mi_last_error", "mi_tune"):
+                     "mi_last_error", "mi_tune", "mi_server_create", "mi_server_submit", "mi_server_wait"):
         assert required in names, required
 
 
@@ -122,3 +122,19 @@ def test_python_binding_refuses_cpu_tensors(L):
     from paper_2411_19702_amd import mi
     with pytest.raises(ValueError):
         mi.mi_all_pairs(torch.zeros((4, 3), dtype=torch.uint8))
+
+
+def test_server_argument_checks_on_host(L):
+    from paper_2411_19702_amd import mi
+    h = ctypes.c_void_p()
+    assert L.mi_server_create(None, 1 << 30, 4, 0) == 1
+    assert L.mi_server_create(ctypes.byref(h), 0, 4, 0) == 1
+    assert L.mi_server_create(ctypes.byref(h), 1 << 30, 0, 0) == 1
+    assert L.mi_server_create(ctypes.byref(h), 1 << 30, 65, 0) == 1
+    assert L.mi_server_create(ctypes.byref(h), 1 << 30, 4, -1) == 1
+    t = ctypes.c_uint64()
+    p = _problem(mi, X=16, out=16)
+    assert L.mi_server_submit(None, ctypes.byref(p), ctypes.byref(t)) == 1
+    assert L.mi_server_poll(None, 1) == 1
+    assert L.mi_server_wait(None, 1, 0.0, None) == 1
+    assert L.mi_server_destroy(None) == 1
