@@ -91,6 +91,104 @@ def cpu_baseline(spec, target_s: float):
     }
 
 
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_batched(dev, reps: int = 3):
+    """256 independent datasets: one persistent launch vs a replayed hipGraph
+    of plain launches vs 256 sequential plain calls (same results, bitwise)."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    specs = synth.specs_batched()
+    Xs = [synth.generate(s, device=dev) for s in specs]
+    outs = [torch.empty((s.n, s.n), dtype=torch.float32, device=dev) for s in specs]
+    probs = [mi.make_problem(X, o) for X, o in zip(Xs, outs)]
+    pu = sum(s.m * s.n * (s.n + 1) / 2 for s in specs)
+    res = {"workload": "batched_256 (m log-uniform [500, 50000], n U[64, 2048])", "datasets": len(specs),
+           "pair_updates": pu}
+    for name, mode in (("persistent", mi.MI_BATCH_PERSISTENT), ("graph", mi.MI_BATCH_GRAPH),
+                       ("sequential", mi.MI_BATCH_SEQUENTIAL)):
+        mi.mi_all_pairs_batched(probs, mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mi.mi_all_pairs_batched(probs, mode=mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"ms": dt * 1e3, "pair_updates_per_s": pu / dt}
+    del Xs, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_served(dev, count: int = 64, load: float = 0.8):
+    """Poisson arrivals of MI requests (m log-uniform [1k, 200k], n log-uniform
+    [128, 8192]): continuous-batching server vs one-at-a-time plain solves, both
+    replayed at lambda = load * mu, mu = the plain one-at-a-time capacity."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    trace = synth.request_trace(count=count, qps=1.0)
+    specs = [r.spec for r in trace]
+    Xs = [synth.generate(s, device=dev) for s in specs]
+    outs = [torch.empty((s.n, s.n), dtype=torch.float32, device=dev) for s in specs]
+    torch.cuda.synchronize()
+    pu = sum(s.m * s.n * (s.n + 1) / 2 for s in specs)
+    # capacity of plain one-at-a-time solves (warm)
+    for X, o in zip(Xs, outs):
+        mi.mi_all_pairs_ex(X, out=o)
+    torch.cuda.synchronize()
+    svc = []
+    for X, o in zip(Xs, outs):
+        t0 = time.perf_counter()
+        mi.mi_all_pairs_ex(X, out=o)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t0)
+    mu = 1.0 / (sum(svc) / len(svc))
+    lam = load * mu
+    arrivals = [r.arrival_s / lam for r in trace]     # the unit-rate Poisson trace scaled to lambda
+
+    def wait_until(t_abs):
+        while True:
+            d = t_abs - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(min(d, 2e-4) if d > 3e-4 else 0)
+
+    # one at a time, first come first served
+    t_start = time.perf_counter()
+    lat_plain, free_at = [], t_start
+    for a, X, o in zip(arrivals, Xs, outs):
+        wait_until(t_start + a)
+        mi.mi_all_pairs_ex(X, out=o)
+        torch.cuda.synchronize()
+        lat_plain.append(time.perf_counter() - (t_start + a))
+    span_plain = time.perf_counter() - t_start
+    # continuous batching
+    with mi.Server(hbm_budget_bytes=200 << 30, max_slots=4) as srv:
+        t_start = time.perf_counter()
+        tickets, late = [], []
+        for a, X, o in zip(arrivals, Xs, outs):
+            wait_until(t_start + a)
+            late.append(time.perf_counter() - (t_start + a))
+            tickets.append(srv.submit(X, o))
+        lat_srv = [lt + srv.wait(t, timeout_s=300) for lt, t in zip(late, tickets)]
+        span_srv = time.perf_counter() - t_start
+        st = srv.stats()
+    del Xs, outs
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"served: {count} Poisson requests, m log-uniform [1000, 200000], n log-uniform [128, 8192]",
+        "mu_req_per_s": mu, "lambda_req_per_s": lam, "budget_bytes": 200 << 30,
+        "server": {"p50_ms": _pct(lat_srv, 50) * 1e3, "p99_ms": _pct(lat_srv, 99) * 1e3,
+                   "pair_updates_per_s": pu / span_srv, "batches": st["batches"],
+                   "max_in_flight": st["max_in_flight"]},
+        "one_at_a_time": {"p50_ms": _pct(lat_plain, 50) * 1e3, "p99_ms": _pct(lat_plain, 99) * 1e3,
+                          "pair_updates_per_s": pu / span_plain},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +202,7 @@ def main() -> int:
     ap.add_argument("--shape", default="", help="M,N: time a random M x N matrix instead of a named workload")
     ap.add_argument("--tile", type=int, default=0, help="force a tile config (1: 128, 2: 256)")
     ap.add_argument("--splits", type=int, default=0, help="force the K-split count")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and served measurements")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB per step "
                          "(reference for the HBM byte counters)")
@@ -205,6 +304,9 @@ def main() -> int:
     }
     del X
     torch.cuda.empty_cache()
+    if not args.no_extras and not args.shape:
+        rec["batched"] = bench_batched(dev)
+        rec["served"] = bench_served(dev)
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
