@@ -34,20 +34,23 @@ WORKLOADS = {
 }
 
 
+KERNEL_SOURCES = ("mi_device.hpp", "mi_internal.hpp", "mi_kernels.hip")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the device-code sources (the kernels and their launch shapes)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_19702_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, launches_per_step: int):
+def load_traffic(workload: str, tile: int, splits: int):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel sources."""
+    were taken on the current kernel sources with the same tile and split count."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -57,6 +60,8 @@ def load_traffic(workload: str, launches_per_step: int):
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    if rec.get("tile") != tile or rec.get("splits") != splits:
         return None
     return rec.get("bytes_per_launch")
 
@@ -96,6 +101,50 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
+def bench_plain(dev, workload: str, steps: int = 30, tune: bool = False):
+    """One named single-dataset workload through mi_all_pairs_ex: median kernel
+    time (HIP events on the launch stream), blocking-call latency, pair-updates/s,
+    fraction of the int8 peak and algorithmic HBM rate (X once + FP32 output)."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    spec = getattr(synth, WORKLOADS[workload])()
+    X = synth.generate(spec, device=dev)
+    m, n = spec.m, spec.n
+    out = torch.empty((n, n), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    tuned = None
+    if tune:
+        tile, splits, best = mi.mi_tune(m, n, X.stride(0))
+        tuned = {"tile": [None, 128, 256][tile], "splits": splits}
+    tile, splits = mi.mi_plan(m, n, X.stride(0))
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        mi.mi_all_pairs_ex(X, out=out, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        mi.mi_all_pairs_ex(X, out=out, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ks = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
+    k = ks[len(ks) // 2]
+    lat = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        mi.mi_all_pairs_ex(X, out=out, stream=stream)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    pu = m * n * (n + 1) / 2
+    nbytes = m * X.stride(0) + 4 * n * n
+    del X, out
+    torch.cuda.empty_cache()
+    return {"workload": workload, "m": m, "n": n, "tile": [None, 128, 256][tile], "splits": splits,
+            "tuned": tuned, "kernel_ms_median": k * 1e3, "call_latency_ms_median": _pct(lat, 50) * 1e3,
+            "pair_updates_per_s": pu / k, "frac_int8_peak": 2 * pu / k / PEAK_INT8_OPS,
+            "hbm_algorithmic_GBps": nbytes / k / 1e9, "frac_hbm_peak": nbytes / k / PEAK_HBM}
+
+
 def bench_batched(dev, reps: int = 3):
     """256 independent datasets: one persistent launch vs a replayed hipGraph
     of plain launches vs 256 sequential plain calls (same results, bitwise)."""
@@ -123,10 +172,12 @@ def bench_batched(dev, reps: int = 3):
     return res
 
 
-def bench_served(dev, count: int = 64, load: float = 0.8):
+def bench_served(dev, count: int = 300, loads=(0.5, 0.8, 0.95, 1.5)):
     """Poisson arrivals of MI requests (m log-uniform [1k, 200k], n log-uniform
-    [128, 8192]): continuous-batching server vs one-at-a-time plain solves, both
-    replayed at lambda = load * mu, mu = the plain one-at-a-time capacity."""
+    [128, 8192], densities U[0.005, 0.5]): the continuous-batching server vs
+    one-at-a-time plain solves, both replayed at lambda = load * mu for each
+    load, mu = the plain one-at-a-time capacity.  Latency runs from the
+    scheduled arrival to result-ready; both paths are warmed first."""
     import torch
     from paper_2411_19702_amd import mi, synth
     trace = synth.request_trace(count=count, qps=1.0)
@@ -135,6 +186,7 @@ def bench_served(dev, count: int = 64, load: float = 0.8):
     outs = [torch.empty((s.n, s.n), dtype=torch.float32, device=dev) for s in specs]
     torch.cuda.synchronize()
     pu = sum(s.m * s.n * (s.n + 1) / 2 for s in specs)
+    budget = 200 << 30
     # capacity of plain one-at-a-time solves (warm)
     for X, o in zip(Xs, outs):
         mi.mi_all_pairs_ex(X, out=o)
@@ -146,8 +198,6 @@ def bench_served(dev, count: int = 64, load: float = 0.8):
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t0)
     mu = 1.0 / (sum(svc) / len(svc))
-    lam = load * mu
-    arrivals = [r.arrival_s / lam for r in trace]     # the unit-rate Poisson trace scaled to lambda
 
     def wait_until(t_abs):
         while True:
@@ -156,37 +206,50 @@ def bench_served(dev, count: int = 64, load: float = 0.8):
                 return
             time.sleep(min(d, 2e-4) if d > 3e-4 else 0)
 
-    # one at a time, first come first served
-    t_start = time.perf_counter()
-    lat_plain, free_at = [], t_start
-    for a, X, o in zip(arrivals, Xs, outs):
-        wait_until(t_start + a)
-        mi.mi_all_pairs_ex(X, out=o)
-        torch.cuda.synchronize()
-        lat_plain.append(time.perf_counter() - (t_start + a))
-    span_plain = time.perf_counter() - t_start
-    # continuous batching
-    with mi.Server(hbm_budget_bytes=200 << 30, max_slots=4) as srv:
-        t_start = time.perf_counter()
-        tickets, late = [], []
-        for a, X, o in zip(arrivals, Xs, outs):
-            wait_until(t_start + a)
-            late.append(time.perf_counter() - (t_start + a))
-            tickets.append(srv.submit(X, o))
-        lat_srv = [lt + srv.wait(t, timeout_s=300) for lt, t in zip(late, tickets)]
-        span_srv = time.perf_counter() - t_start
-        st = srv.stats()
+    res = {"workload": f"served: {count} Poisson requests, m log-uniform [1000, 200000], "
+                       f"n log-uniform [128, 8192], densities U[0.005, 0.5]",
+           "mu_req_per_s": mu, "budget_bytes": budget, "loads": []}
+    with mi.Server(hbm_budget_bytes=budget, max_slots=4) as srv:
+        for t in [srv.submit(X, o) for X, o in zip(Xs, outs)]:      # warm the server's streams
+            srv.wait(t, timeout_s=300)
+        for load in loads:
+            lam = load * mu
+            arrivals = [r.arrival_s / lam for r in trace]     # the unit-rate Poisson trace scaled to lambda
+            # one at a time, first come first served
+            t_start = time.perf_counter()
+            lat_plain = []
+            for a, X, o in zip(arrivals, Xs, outs):
+                wait_until(t_start + a)
+                mi.mi_all_pairs_ex(X, out=o)
+                torch.cuda.synchronize()
+                lat_plain.append(time.perf_counter() - (t_start + a))
+            span_plain = time.perf_counter() - t_start
+            # continuous batching
+            st0 = srv.stats()
+            t_start = time.perf_counter()
+            tickets, late = [], []
+            for a, X, o in zip(arrivals, Xs, outs):
+                wait_until(t_start + a)
+                late.append(time.perf_counter() - (t_start + a))
+                tickets.append(srv.submit(X, o))
+            lat_srv = [lt + srv.wait(t, timeout_s=300) for lt, t in zip(late, tickets)]
+            span_srv = time.perf_counter() - t_start
+            st = srv.stats()
+            res["loads"].append({
+                "load": load, "lambda_req_per_s": lam,
+                "server": {"p50_ms": _pct(lat_srv, 50) * 1e3, "p99_ms": _pct(lat_srv, 99) * 1e3,
+                           "pair_updates_per_s": pu / span_srv, "batches": st["batches"] - st0["batches"],
+                           "max_in_flight": st["max_in_flight"]},
+                "one_at_a_time": {"p50_ms": _pct(lat_plain, 50) * 1e3, "p99_ms": _pct(lat_plain, 99) * 1e3,
+                                  "pair_updates_per_s": pu / span_plain},
+            })
+            print(f"[served] load {load}: server p50 {res['loads'][-1]['server']['p50_ms']:.2f} ms "
+                  f"p99 {res['loads'][-1]['server']['p99_ms']:.2f} ms; one-at-a-time "
+                  f"p50 {res['loads'][-1]['one_at_a_time']['p50_ms']:.2f} ms "
+                  f"p99 {res['loads'][-1]['one_at_a_time']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
     del Xs, outs
     torch.cuda.empty_cache()
-    return {
-        "workload": f"served: {count} Poisson requests, m log-uniform [1000, 200000], n log-uniform [128, 8192]",
-        "mu_req_per_s": mu, "lambda_req_per_s": lam, "budget_bytes": 200 << 30,
-        "server": {"p50_ms": _pct(lat_srv, 50) * 1e3, "p99_ms": _pct(lat_srv, 99) * 1e3,
-                   "pair_updates_per_s": pu / span_srv, "batches": st["batches"],
-                   "max_in_flight": st["max_in_flight"]},
-        "one_at_a_time": {"p50_ms": _pct(lat_plain, 50) * 1e3, "p99_ms": _pct(lat_plain, 99) * 1e3,
-                          "pair_updates_per_s": pu / span_plain},
-    }
+    return res
 
 
 def main() -> int:
@@ -202,7 +265,10 @@ def main() -> int:
     ap.add_argument("--shape", default="", help="M,N: time a random M x N matrix instead of a named workload")
     ap.add_argument("--tile", type=int, default=0, help="force a tile config (1: 128, 2: 256)")
     ap.add_argument("--splits", type=int, default=0, help="force the K-split count")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip the extra measurements")
+    ap.add_argument("--extras", default="configs,batched,served",
+                    help="comma list of extra measurements: configs (the 1000 x 200 and 100000 x 1024 "
+                         "workloads), batched (256 datasets), served (Poisson request trace)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB per step "
                          "(reference for the HBM byte counters)")
@@ -271,7 +337,7 @@ def main() -> int:
     pu_per_step = m * n * (n + 1) / 2
     value = pu_per_step * args.steps / wall
     achieved = 2.0 * pu_per_step / avg_kernel_s
-    traffic = load_traffic(args.workload, 1)
+    traffic = load_traffic(args.workload, [None, 128, 256][tile], splits)
     rec = {
         "metric": "MI pair-updates/s (m*n(n+1)/2) & % int8 MFMA peak; p50/p99 request latency",
         "value": value,
@@ -304,8 +370,13 @@ def main() -> int:
     }
     del X
     torch.cuda.empty_cache()
-    if not args.no_extras and not args.shape:
+    extras = set() if (args.no_extras or args.shape) else set(args.extras.split(","))
+    if "configs" in extras:
+        rec["configs"] = [bench_plain(dev, "small_1000x200"), bench_plain(dev, "mid_100000x1024"),
+                          bench_plain(dev, "mid_100000x1024", tune=True)]
+    if "batched" in extras:
         rec["batched"] = bench_batched(dev)
+    if "served" in extras:
         rec["served"] = bench_served(dev)
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)

@@ -11,6 +11,12 @@
  *     launch pulling work units of all of them; a lone request runs as a
  *     plain launch) on a free slot, so work of newly admitted requests runs
  *     on the device next to requests that are still running,
+ *   - sizes batches by an estimate of each request's device time: a large
+ *     request (about 250 us or more alone) runs by itself and only one large
+ *     request runs at a time, small requests are grouped up to about 400 us
+ *     of summed work and run on the other slots (they may start before a
+ *     large request that waits for the running one; a request that waits
+ *     for budget is never overtaken),
  *   - detects completion with events and records each request's latency from
  *     submission to completion.
  * A request's results are bitwise the same whether it runs alone or in a

@@ -1,11 +1,24 @@
 // mi_server.cpp -- continuous-batching request loop (include/mi_server.h).
 //
 // One host thread per server.  Requests wait in a FIFO; whenever a slot (a
-// HIP stream) is free the loop admits every waiting request, in order, that
-// fits the HBM budget next to what is already running, and launches them
-// together (one persistent batched launch, or a plain launch for a single
-// request) on that slot.  Batches on different slots run concurrently on the
-// device.  Completion is detected by polling one event per batch.
+// HIP stream) is free the loop admits waiting requests that fit the HBM
+// budget next to what is already running and launches them on that slot.
+// Batches on different slots run concurrently on the device.  Completion is
+// detected by polling one event per batch.
+//
+// Batch formation uses a cost estimate per request (pair updates at a
+// sustained rate plus a launch floor), so that small requests are never tied
+// to a large one:
+//   - a large request (estimate >= kLargeUs) runs alone, as a plain launch;
+//   - consecutive small requests are launched together, as one persistent
+//     launch, until their summed estimate reaches kBatchCapUs;
+//   - one large request runs at a time (alone it already fills the device;
+//     two at once only share it and both finish later), first come first
+//     served among large requests; small requests use the other slots, and
+//     while the head of the queue is a large request that has to wait for
+//     the running one, small requests behind it may start first.
+// Admission against the budget stays first come, first served: a request
+// that does not fit waits, and nothing behind it overtakes it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +44,7 @@ enum ReqState { kWaiting = 0, kRunning = 1, kDone = 2 };
 struct Req {
   mi_problem p;
   size_t bytes = 0;
+  double est_us = 0.0;
   Clock::time_point t_submit, t_done;
   int state = kWaiting;
   mi_status status = MI_OK;
@@ -41,9 +55,12 @@ struct Batch {
   hipEvent_t ev = nullptr;
   int slot = -1;
   size_t bytes = 0;
+  bool large = false;
 };
 
-constexpr int kMaxBatch = 256;  // requests launched together at most
+constexpr int kMaxBatch = 256;          // requests launched together at most
+constexpr double kLargeUs = 250.0;      // estimate from which a request runs alone
+constexpr double kBatchCapUs = 400.0;   // summed estimate of one batch of small requests
 
 }  // namespace
 
@@ -89,6 +106,14 @@ size_t request_bytes(const mi_problem& p, int64_t ldx) {
 
 double seconds(Clock::duration d) { return std::chrono::duration<double>(d).count(); }
 
+// Device time of a request alone, in microseconds: a launch floor, the pair
+// updates m n (n+1) / 2 at a sustained 1e15 per second, and the n^2 FP32
+// output at 4 TB/s.  Only the ratio between requests matters for batching.
+double estimate_us(const mi_problem& p) {
+  const double n = (double)p.n, m = (double)p.m;
+  return 10.0 + m * n * (n + 1.0) / 2.0 / 1.0e9 + 4.0 * n * n / 4.0e6;
+}
+
 }  // namespace
 
 void mi_server::finish_batch(Batch& b, mi_status st, Clock::time_point now) {
@@ -126,25 +151,45 @@ void mi_server::loop() {
     }
     if (progressed) cv_done.notify_all();
 
-    // 2. Admission: everything at the head of the queue that fits, onto one free slot.
-    int slot = -1;
+    // 2. Admission onto one free slot (see the policy at the top of this file).
+    int slot = -1, large_running = 0;
     for (int s = 0; s < nslots; ++s)
-      if (!slot_busy[s]) {
-        slot = s;
-        break;
-      }
+      if (!slot_busy[s] && slot < 0) slot = s;
+    for (const auto& rb : running) large_running += rb.large ? 1 : 0;
     if (slot >= 0 && !waiting.empty()) {
       Batch b;
       b.slot = slot;
       std::vector<mi_problem> probs;
-      while (!waiting.empty() && (int)probs.size() < kMaxBatch) {
-        Req& r = reqs[waiting.front()];
-        if (in_flight + b.bytes + r.bytes > budget) break;  // first come, first served
+      const bool large_ok = large_running == 0;
+      auto take = [&](std::deque<uint64_t>::iterator it) {
+        Req& r = reqs[*it];
         b.bytes += r.bytes;
-        b.tickets.push_back(waiting.front());
+        b.tickets.push_back(*it);
         probs.push_back(r.p);
         r.state = kRunning;
-        waiting.pop_front();
+        return waiting.erase(it);
+      };
+      auto it = waiting.begin();
+      const Req& head = reqs[*it];
+      if (head.est_us >= kLargeUs && large_ok) {
+        if (in_flight + head.bytes <= budget) {
+          take(it);
+          b.large = true;
+        }
+      } else {
+        // Small requests from the head on; a large head without a slot is
+        // passed over, any other request that is large or over budget ends
+        // the batch.
+        double cost = 0.0;
+        if (head.est_us >= kLargeUs) ++it;
+        while (it != waiting.end() && (int)probs.size() < kMaxBatch) {
+          const Req& r = reqs[*it];
+          if (r.est_us >= kLargeUs) break;
+          if (in_flight + b.bytes + r.bytes > budget) break;
+          if (!probs.empty() && cost + r.est_us > kBatchCapUs) break;
+          cost += r.est_us;
+          it = take(it);
+        }
       }
       if (!probs.empty()) {
         slot_busy[slot] = 1;
@@ -234,6 +279,7 @@ mi_status mi_server_submit(mi_server* s, const mi_problem* p, uint64_t* ticket) 
   Req r;
   r.p = *p;
   r.bytes = request_bytes(*p, ldx);
+  r.est_us = estimate_us(*p);
   r.t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
   if (r.bytes > s->budget) {
