@@ -72,7 +72,7 @@ typedef enum mi_epilogue {
 typedef enum mi_tile {
   MI_TILE_AUTO = 0,
   MI_TILE_128 = 1,  /* 128 x 128 output tile, 4 waves of 64 x 64 */
-  MI_TILE_256 = 2   /* 256 x 256 output tile, 4 waves of 128 x 128 */
+  MI_TILE_256 = 2   /* 256 x 256 output tile, 8 waves of 128 x 64 */
 } mi_tile;
 
 typedef struct mi_problem {

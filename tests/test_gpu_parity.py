@@ -162,7 +162,7 @@ def _sample_columns(spec, n_random: int, seed: int, extra=()):
     return sorted(cols)
 
 
-@pytest.mark.parametrize("epi", [0, 1])
+@pytest.mark.parametrize("epi", [0, 1, 2])
 def test_mid_workload_sampled(epi):
     spec = synth.spec_mid()
     say(f"[parity] mid 100000x1024 epi={epi}")
@@ -174,11 +174,12 @@ def test_mid_workload_sampled(epi):
     say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
 
 
-def test_large_workload_sampled():
+@pytest.mark.parametrize("epi", [0, 1])
+def test_large_workload_sampled(epi):
     spec = synth.spec_large()
-    say("[parity] large 1000000x4096")
+    say(f"[parity] large 1000000x4096 epi={epi}")
     X = _gen(spec)
-    out, n11, cs = run_gpu(X)
+    out, n11, cs = run_gpu(X, epilogue=epi)
     del X
     torch.cuda.empty_cache()
     cols = _sample_columns(spec, 8, 2)
