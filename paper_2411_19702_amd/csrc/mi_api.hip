@@ -163,20 +163,12 @@ const int32_t* tile_table(int ntp, hipError_t* err) {
 // ----------------------------------------------------------------- planner --
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Workspace of a plan with several K splits: per tile BT^2 int32 partial
+// counts, then 2 BT partial column sums, then one arrival counter per tile.
 size_t workspace_bytes(const Plan& pl) {
   if (pl.splits <= 1) return 0;
   const int64_t per = (int64_t)pl.bt * pl.bt + 2 * pl.bt + 1;
   return (size_t)(pl.ntiles * per * sizeof(int32_t) + 256);
-}
-
-// Unit-to-XCD mapping of the plain launch.  Tile blocks per XCD (map 0) keep
-// every XCD on the same rows, which the last-level cache then shares; it
-// measured faster than K splits per XCD (map 1) on the 1M x 4096 workload.
-static int choose_map(const Plan& pl) {
-  const char* e = getenv("MI_XCD_MAP");
-  if (e && (e[0] == '0' || e[0] == '1')) return e[0] - '0';
-  (void)pl;
-  return 0;
 }
 
 Plan make_plan(int64_t m, int64_t n, int cfg, int splits) {
@@ -186,35 +178,35 @@ Plan make_plan(int64_t m, int64_t n, int cfg, int splits) {
   pl.ntp = (int)cdiv(std::max<int64_t>(n, 1), pl.bt);
   pl.ntiles = pl.ntp * (pl.ntp + 1) / 2;
   pl.tpx = (int)cdiv(pl.ntiles, 8);
-  const int64_t steps = cdiv(m, KT);
+  pl.ksteps = cdiv(m, KT);
   if (splits < 1) splits = 1;
-  if (splits > steps) splits = (int)steps;
-  const int64_t per = cdiv(steps, splits);
-  pl.kchunk = (int)(per * KT);
+  if (splits > pl.ksteps) splits = (int)pl.ksteps;
+  pl.kchunk = (int)(cdiv(pl.ksteps, splits) * KT);
   pl.splits = (int)cdiv(m, pl.kchunk);
-  pl.map = choose_map(pl);
   return pl;
 }
 
-// Heuristic when the tuner has no entry: the plain grid is 8 * tpx * splits
-// workgroups (tiles split evenly over the 8 XCDs); pick the number of K splits
-// that fills the chip's slots in whole waves, keeping at least kMinRows rows
-// per split so that the workspace flush stays small next to the streamed rows.
-static int heuristic_splits(int64_t m, const Plan& p1, int slots) {
-  const int64_t kMinRows = 4096;
+// Heuristic when the tuner has no entry.  The plain grid is 8 * tpx * splits
+// workgroups (tiles split evenly over the 8 XCDs), and one workgroup per CU
+// keeps a CU's matrix cores and LDS busy (a second one per CU measured
+// slower), so the launch runs in ceil(grid / CUs) waves of units.  A unit
+// costs its rows plus, when the tile is split, about kPublishRows rows' worth
+// of time to publish its partial counts (measured: ~20 us against ~0.6 us
+// per 64-row step).  Pick the split count with the least modelled time,
+// keeping at least kMinRows rows per split.
+static int heuristic_splits(int64_t m, const Plan& p1, int cus) {
+  const int64_t kMinRows = 4096, kPublishRows = 2048;
   const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(512, m / kMinRows));
   int best = 1;
-  double best_eff = 0.0;
+  double best_t = 1e300;
   for (int64_t s = 1; s <= smax; ++s) {
-    const double busy = (double)p1.ntiles * (double)s;      // units with work
-    const double grid = 8.0 * p1.tpx * (double)s;
-    const double waves = std::ceil(grid / slots);
-    const double eff = busy / (waves * slots);
-    if (eff > best_eff + 0.02) {
-      best_eff = eff;
+    const double waves = std::ceil(8.0 * p1.tpx * (double)s / cus);
+    const double rows = (double)cdiv(p1.ksteps, s) * KT + (s > 1 ? (double)kPublishRows : 0.0);
+    const double t = waves * rows;
+    if (t < best_t * 0.99) {  // prefer fewer splits unless clearly faster
+      best_t = t;
       best = (int)s;
     }
-    if (eff > 0.96) break;
   }
   return best;
 }
@@ -253,16 +245,16 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
   if (s != MI_OK) return s;
   int cfg = tile_req == MI_TILE_256 ? 1 : (tile_req == MI_TILE_128 ? 0 : -1);
   int splits = splits_req;
-  if (cfg < 0 || splits <= 0) {
+  if (splits <= 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(shape_key(m, n, aligned));
-    if (it != g_tuned.end()) {
-      if (cfg < 0) cfg = it->second.cfg;
-      if (splits <= 0 && cfg == it->second.cfg) splits = it->second.splits;
+    if (it != g_tuned.end() && (cfg < 0 || cfg == it->second.cfg)) {
+      cfg = it->second.cfg;
+      splits = it->second.splits;
     }
   }
   if (cfg < 0) cfg = heuristic_cfg(m, n);
-  if (splits <= 0) splits = heuristic_splits(m, make_plan(m, n, cfg, 1), di.cus * di.occ[cfg]);
+  if (splits <= 0) splits = heuristic_splits(m, make_plan(m, n, cfg, 1), di.cus);
   *out = make_plan(m, n, cfg, splits);
   return MI_OK;
 }
@@ -303,12 +295,12 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
   P.tiles = tiles;
   P.ntp = pl.ntp;
   P.ntiles = pl.ntiles;
-  P.splits = pl.splits;
+  P.ksteps = (int32_t)pl.ksteps;
   P.kchunk = pl.kchunk;
-  P.tiles_per_xcd = pl.tpx;
-  P.map = pl.map;
   P.epi = p->epilogue;
   P.tau = p->fallback_tau > 0.0f ? p->fallback_tau : 1e-3f;
+  P.splits = pl.splits;
+  P.tiles_per_xcd = pl.tpx;
   if (pl.splits > 1 && ws) {
     int32_t* base = reinterpret_cast<int32_t*>(ws);
     P.ws_n11 = base;
@@ -652,8 +644,10 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   DeviceInfo di;
   mi_status s = device_info(&di);
   if (s != MI_OK) return s;
-  // The kernel's time does not depend on the data, and unaligned layouts are
-  // repacked to a packed pitch first, so time on a zero matrix of that pitch.
+  // Unaligned layouts are repacked to a packed pitch first, so time on a
+  // matrix of that pitch.  It is all ones: every count is nonzero, so every
+  // split-K partial is published (the kernels skip zero partials), which is
+  // the costly case.
   const bool aligned = ldx % 16 == 0;
   const int64_t ld = aligned ? ldx : packed_pitch(n);
   uint8_t* X = nullptr;
@@ -672,25 +666,25 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   hipEvent_t e0 = nullptr, e1 = nullptr;
   Tuned best{-1, 0, 1e30};
   auto body = [&]() -> mi_status {
-    HIPCHK(hipMemset(X, 0, xbytes));
+    HIPCHK(hipMemset(X, 1, xbytes));
     HIPCHK(hipStreamCreate(&st));
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     hipError_t te;
     for (int cfg = 0; cfg < kNumCfg; ++cfg) {
       const Plan p1 = make_plan(m, n, cfg, 1);
-      const int64_t steps = cdiv(m, KT);
       std::vector<int> cands;
-      for (int sp : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
-        if (sp <= steps) cands.push_back(sp);
-      cands.push_back(heuristic_splits(m, p1, di.cus * di.occ[cfg]));
+      for (int sp = 1; sp <= 16; ++sp) cands.push_back(sp);
+      for (int sp : {20, 24, 32, 48, 64, 96, 128, 192, 256}) cands.push_back(sp);
+      cands.push_back(heuristic_splits(m, p1, di.cus));
       std::sort(cands.begin(), cands.end());
       cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
       const int32_t* tiles = tile_table(p1.ntp, &te);
       if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(te));
       for (int sp : cands) {
+        if (sp > p1.ksteps) continue;
         const Plan pl = make_plan(m, n, cfg, sp);
-        if ((double)pl.ntiles * pl.splits > 4.0e6) continue;
+        if (pl.splits != sp || (double)pl.ntiles * pl.splits > 4.0e6) continue;
         void* ws = nullptr;
         mi_status ss = workspace(st, 0, workspace_bytes(pl), &ws);
         if (ss != MI_OK) return ss;

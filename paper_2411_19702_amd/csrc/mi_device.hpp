@@ -1,6 +1,7 @@
 // mi_device.hpp -- device side of the fused all-pairs binary MI kernel (gfx950).
 //
-// One work unit = (dataset, output tile (I, J) with I <= J, K-split s).  A unit
+// One work unit = (dataset, output tile (I, J) with I <= J, rows [k0, k1)).
+// A unit
 //   1. streams its rows [k0, k1) of the two column panels X[:, I] and X[:, J]
 //      from HBM into a 4-stage LDS ring with buffer->LDS DMA loads (no
 //      registers, no VALU); rows past k1 come back as zeros from the buffer
@@ -15,8 +16,9 @@
 //   4. accumulates the column sums c_I, c_J of its rows from the operand
 //      registers with bytewise adds folded by v_dot4_u32_u8 (Section 2 step 3
 //      / Section 3.1 "Term 2");
-//   5. with several K-splits, adds its partial counts into a per-tile int32
-//      workspace; the last unit to arrive at a tile reads the totals back,
+//   5. when it covers only part of the rows, adds its partial counts into a
+//      per-tile int32 workspace and its row steps into the tile's arrival
+//      counter; the unit that completes the count reads the totals back,
 //      clears the workspace, and alone runs the epilogue;
 //   6. epilogue: derives n10, n01, n00 from n11, c and m (Section 3.1,
 //      Eq. 6/7), evaluates MI (Eq. 2/3) per element in FP32 (FP64 on demand)
@@ -29,6 +31,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace mi {
 
@@ -71,18 +75,18 @@ struct ProbDev {
   float* out;
   int32_t* n11_out;     // optional
   int32_t* colsum_out;  // optional
-  int32_t* ws_n11;      // splits > 1: ntiles * BT * BT int32, all zero between calls
-  int32_t* ws_col;      // splits > 1: ntiles * 2 * BT int32
-  int32_t* counters;    // splits > 1: ntiles int32
+  int32_t* ws_n11;      // partial units: ntiles * BT * BT int32, all zero between calls
+  int32_t* ws_col;      // partial units: ntiles * 2 * BT int32
+  int32_t* counters;    // partial units: ntiles int32 (row steps arrived)
   const int32_t* tiles; // tile order: ntiles entries of (I << 16) | J
   int32_t ntp;          // panels = ceil(n / BT)
   int32_t ntiles;       // ntp (ntp + 1) / 2
-  int32_t splits;
+  int32_t ksteps;       // row steps of a whole tile = ceil(m / KT)
+  int32_t splits;       // K splits per tile
   int32_t kchunk;       // rows per split, a multiple of KT
+  int32_t tiles_per_xcd;  // plain launch: tiles owned by each of the 8 XCDs
   int32_t epi;          // mi_epilogue
   float tau;
-  int32_t tiles_per_xcd;  // plain launch, map 0: tiles owned by each of the 8 XCDs
-  int32_t map;            // plain launch: 0 = tile blocks per XCD, 1 = K splits per XCD
 };
 
 // ---------------------------------------------------------------------------
@@ -92,13 +96,15 @@ struct ProbDev {
 // summed as (t11 + t00) + (t10 + t01).  Contraction into FMAs is disabled so
 // the compiler cannot break that symmetry.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float cell32(int nxy, int nx, int ny, float fm) {
+// FP32 cell term n_xy log2(n_xy m / (n_x n_y)), with the reciprocals of the
+// two marginal counts passed in: the ratio is (n_xy m) (r_x r_y), three
+// multiplies and no division.  (r_x r_y) is one commutative multiply, so the
+// term of pair (j, i) is bitwise the one of (i, j).
+__device__ __forceinline__ float cell32(int nxy, float fm, float rx, float ry) {
 #pragma clang fp contract(off)
   if (nxy <= 0) return 0.0f;                      // 0 log 0 = 0
   const float fn = (float)nxy;
-  const float num = fn * fm;                      // n_xy * m
-  const float den = (float)nx * (float)ny;        // n_x * n_y
-  return fn * __log2f(__fdividef(num, den));
+  return fn * __log2f((fn * fm) * (rx * ry));
 }
 
 __device__ __forceinline__ double cell64(int nxy, int nx, int ny, int m) {
@@ -119,20 +125,21 @@ __device__ __forceinline__ float mi_value64(int m, int ci, int cj, int n11) {
   return (float)(((d11 + d00) + (d10 + d01)) / (double)m);
 }
 
-__device__ __forceinline__ float mi_value(int m, int ci, int cj, int n11, int epi, float tau) {
+// MI of one pair in the requested mode.  r1x = 1 / c_x and r0x = 1 / (m - c_x)
+// (unused where the matching cell count is 0, so 1 / 0 there is harmless);
+// rfm = 1 / m.
+__device__ __forceinline__ float mi_value(int m, float fm, float rfm, int ci, int cj, float r1i, float r0i,
+                                          float r1j, float r0j, int n11, int epi, float tau) {
 #pragma clang fp contract(off)
   if (epi == 2) return mi_value64(m, ci, cj, n11);
-  const int n10 = ci - n11;   // X_i = 1, X_j = 0
-  const int n01 = cj - n11;   // X_i = 0, X_j = 1
-  const int ni0 = m - ci;     // marginal count of X_i = 0
-  const int nj0 = m - cj;     // marginal count of X_j = 0
-  const int n00 = ni0 - n01;  // = m - c_i - c_j + n11, without overflow
-  const float fm = (float)m;
-  const float t11 = cell32(n11, ci, cj, fm);
-  const float t00 = cell32(n00, ni0, nj0, fm);
-  const float t10 = cell32(n10, ci, nj0, fm);
-  const float t01 = cell32(n01, ni0, cj, fm);
-  const float v = ((t11 + t00) + (t10 + t01)) / fm;
+  const int n10 = ci - n11;         // X_i = 1, X_j = 0
+  const int n01 = cj - n11;         // X_i = 0, X_j = 1
+  const int n00 = (m - ci) - n01;   // = m - c_i - c_j + n11, without overflow
+  const float t11 = cell32(n11, fm, r1i, r1j);
+  const float t00 = cell32(n00, fm, r0i, r0j);
+  const float t10 = cell32(n10, fm, r1i, r0j);
+  const float t01 = cell32(n01, fm, r0i, r1j);
+  const float v = ((t11 + t00) + (t10 + t01)) * rfm;
   if (epi == 1 && v < tau) return mi_value64(m, ci, cj, n11);
   return v;
 }
@@ -187,13 +194,14 @@ __device__ __forceinline__ v4i read_frag(const uint8_t* p) {
 
 __device__ __forceinline__ uint32_t sgpr(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Buffer descriptor for the rows [ks, min(ks + KT, kend)) of X: reads at byte
-// offsets past that range return zeros.  ks and kend are workgroup-uniform.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t stage_rsrc(const ProbDev& P, int ks, int kend) {
-  const int rows = max(0, min(kend - ks, KT));
-  const uint64_t base = (uint64_t)(P.X + (int64_t)min(ks, P.m - 1) * P.ldx);
+// Buffer descriptor for one stage: `rem` rows of X are left from `base` on
+// (rem <= 0 past the end of the unit); reads at byte offsets past
+// min(rem, KT) rows return zeros and touch no memory.  All arguments are
+// workgroup-uniform scalars.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stage_rsrc(uint64_t base, int rem, int ldx) {
+  const int rows = rem >= KT ? KT : max(rem, 0);
   const uint32_t lo = sgpr((uint32_t)base), hi = sgpr((uint32_t)(base >> 32));
-  const int nrec = (int)sgpr((uint32_t)(rows * (int)P.ldx));
+  const int nrec = (int)sgpr((uint32_t)(rows * ldx));
   return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), 0, nrec, 0x00020000);
 }
 
@@ -206,16 +214,17 @@ __device__ __forceinline__ void tile_ij(const ProbDev& P, int t, int& I, int& J)
 
 // LDS of one workgroup: the four ring slots are separate objects (so the
 // compiler can tell which DMA each operand read depends on), plus the column
-// sums and a flag.
+// sums and a flag, and the epilogue's per-column reciprocals.
 template <class C>
 struct Smem {
   uint8_t* slot[4];
   int32_t* cols;  // 2 * BT + 4 int32
+  float* rcp;     // 4 * BT float
 };
 
 // One work unit.
 template <class C>
-__device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const Smem<C>& sm) {
+__device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1, const Smem<C>& sm) {
 #if defined(__HIP_DEVICE_COMPILE__)  // device-only body (gfx950 builtins and asm)
   constexpr int BT = C::BT, FM = C::FM, FN = C::FN;
   const int tid = threadIdx.x;
@@ -226,9 +235,8 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
   int I, J;
   tile_ij(P, t, I, J);
   const bool diag = (I == J);
-  const int k0 = s * P.kchunk;
-  const int k1 = min(P.m, k0 + P.kchunk);
   const int nsteps = (k1 - k0 + KT - 1) / KT;
+  const bool whole = (k0 == 0 && k1 == P.m);
 
   int32_t* sColA = sm.cols;
   int32_t* sColB = sColA + BT;
@@ -251,19 +259,38 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
     voff[i] = row * (int)P.ldx + col0 + 16 * seg;
     ldsoff[i] = (uint32_t)R * 1024u;
   }
-  auto dma_stage = [&](int ks, uint8_t* slot) {
-    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(P, ks, k1);
+  // Stage j of the unit starts at row k0 + j KT; its base address advances by
+  // KT * ldx bytes per stage (scalar adds, no per-stage multiplies).
+  const int ldx32 = (int)P.ldx;
+  const uint64_t stage_bytes = (uint64_t)KT * (uint64_t)P.ldx;
+  const uint64_t xk0 = (uint64_t)(P.X + (int64_t)k0 * P.ldx);
+  auto dma_stage = [&](uint64_t base, int rem, uint8_t* slot) {
+    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(base, rem, ldx32);
 #pragma unroll
     for (int i = 0; i < C::LOADS; ++i)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (MI_LDS void*)(slot + ldsoff[i]), 16, voff[i], 0, 0, 0);
   };
 
+  // Column sums: the WGN waves that share an A panel block each sum SA of its
+  // FM fragments, and the WGM waves that share a B block each sum SB of its FN
+  // fragments, so each column of both panels is summed by exactly one wave
+  // and the work is the same for all waves.  Register fragment a of a wave
+  // holds column block (a + ra) mod FM of its A block (b: (b + rb) mod FN of
+  // its B block); the rotation puts the fragments the wave sums at registers
+  // 0 .. SA-1 (0 .. SB-1), so the loop sums fixed registers, without branches.
+  constexpr int SA = FM / C::WGN, SB = FN / C::WGM;
+  static_assert(SA * C::WGN == FM && SB * C::WGM == FN, "column sums split evenly over the waves");
+  static_assert((FM & (FM - 1)) == 0 && (FN & (FN - 1)) == 0, "fragment counts are powers of two");
+  const int ra = wn * SA, rb = wm * SB;
+  auto blk_a = [&](int a) { return (a + ra) & (FM - 1); };
+  auto blk_b = [&](int b) { return (b + rb) & (FN - 1); };
+
   // Operand read offsets (inside a stage) for this lane's fragments.
   uint32_t aoff[FM], boff[FN];
 #pragma unroll
-  for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off<BT>((wm * C::WTM) / 16 + 2 * a, lane);
+  for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off<BT>((wm * C::WTM) / 16 + 2 * blk_a(a), lane);
 #pragma unroll
-  for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off<BT>((wn * C::WTN) / 16 + 2 * b, lane));
+  for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off<BT>((wn * C::WTN) / 16 + 2 * blk_b(b), lane));
 
   v16i acc[FM][FN];
 #pragma unroll
@@ -272,14 +299,15 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
     for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
-  // Column sums: every wave sums one of its A fragments (index wn) and one of
-  // its B fragments (index wm), so each column of both panels is summed by
-  // exactly one wave and the work is the same for all waves.  Bytes are 0/1:
-  // the four dwords of a fragment half add bytewise without carries (<= 4 per
-  // byte), accumulate bytewise for four steps (<= 32 per byte), and are folded
-  // into 32-bit totals with v_dot4 once per four steps.
-  static_assert(FM == C::WGN && FN == C::WGM, "one summed fragment per wave and panel");
-  uint32_t pkA = 0u, pkB = 0u, csA = 0u, csB = 0u;
+  // Column-sum registers.  Bytes are 0/1: the four dwords of a fragment half
+  // add bytewise without carries (<= 4 per byte), accumulate bytewise for
+  // four steps (<= 32 per byte), and are folded into 32-bit totals with v_dot4
+  // once per four steps.
+  uint32_t pkA[SA], pkB[SB], csA[SA], csB[SB];
+#pragma unroll
+  for (int x = 0; x < SA; ++x) pkA[x] = csA[x] = 0u;
+#pragma unroll
+  for (int y = 0; y < SB; ++y) pkB[y] = csB[y] = 0u;
 
   // Fragments are read one K half ahead of their MFMAs (two register sets):
   // while the MFMAs of one half execute, the wave reads the next half, and
@@ -300,11 +328,16 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
       for (int b = 0; b < FN; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
-      if (a == wn) pkA += ((uint32_t)fa[a].x + (uint32_t)fa[a].y) + ((uint32_t)fa[a].z + (uint32_t)fa[a].w);
+    for (int x = 0; x < SA; ++x) pkA[x] += ((uint32_t)fa[x].x + (uint32_t)fa[x].y) + ((uint32_t)fa[x].z + (uint32_t)fa[x].w);
 #pragma unroll
-    for (int b = 0; b < FN; ++b)
-      if (b == wm) pkB += ((uint32_t)fb[b].x + (uint32_t)fb[b].y) + ((uint32_t)fb[b].z + (uint32_t)fb[b].w);
+    for (int y = 0; y < SB; ++y) pkB[y] += ((uint32_t)fb[y].x + (uint32_t)fb[y].y) + ((uint32_t)fb[y].z + (uint32_t)fb[y].w);
+    // Keep each half's sums here: left alone, the compiler may re-associate
+    // the chain and defer all adds to the end of the unrolled loop, which
+    // keeps every fragment register of four steps alive.
+#pragma unroll
+    for (int x = 0; x < SA; ++x) asm volatile("" : "+v"(pkA[x]));
+#pragma unroll
+    for (int y = 0; y < SB; ++y) asm volatile("" : "+v"(pkB[y]));
   };
   // Stage `step + 1` complete for every wave, and every wave done reading the
   // slot that the next DMA refills: this wave waits for its own DMA of that
@@ -316,21 +349,26 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
 
   // Prologue: stages 0 .. 2 in flight in slots 0 .. 2; once stage 0 is in,
   // stage 3 goes to slot 3 and the first half of stage 0 is read.
-  dma_stage(k0, sm.slot[0]);
-  dma_stage(k0 + KT, sm.slot[1]);
-  dma_stage(k0 + 2 * KT, sm.slot[2]);
+  const int rows = k1 - k0;
+  dma_stage(xk0, rows, sm.slot[0]);
+  dma_stage(xk0 + stage_bytes, rows - KT, sm.slot[1]);
+  dma_stage(xk0 + 2 * stage_bytes, rows - 2 * KT, sm.slot[2]);
   stage_barrier();
-  dma_stage(k0 + 3 * KT, sm.slot[3]);
+  dma_stage(xk0 + 3 * stage_bytes, rows - 3 * KT, sm.slot[3]);
   read_half(sm.slot[0], 0, fa0, fb0);
+  uint64_t dbase = xk0 + 4 * stage_bytes;  // stage step + 4, loaded during step `step`
+  int drem = rows - 4 * KT;
 
   // Step `step` (stage in slot cur, the next stage in slot nxt).
-  auto do_step = [&](int step, uint8_t* cur, uint8_t* nxt) {
+  auto do_step = [&](uint8_t* cur, uint8_t* nxt) {
     read_half(cur, 1, fa1, fb1);
     __builtin_amdgcn_sched_barrier(0);
     mma_half(fa0, fb0);
     __builtin_amdgcn_sched_barrier(0);
     stage_barrier();
-    dma_stage(k0 + (step + 4) * KT, cur);  // stage step + 4 into the slot just consumed
+    dma_stage(dbase, drem, cur);  // stage step + 4 into the slot just consumed
+    dbase += stage_bytes;
+    drem -= KT;
     read_half(nxt, 0, fa0, fb0);
     __builtin_amdgcn_sched_barrier(0);
     mma_half(fa1, fb1);
@@ -340,26 +378,35 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
   // Unrolled over the four slots; a unit whose step count is not a multiple
   // of four runs up to three extra steps on zeros (rows past k1 read as zero).
   for (int step = 0; step < nsteps; step += 4) {
-    do_step(step, sm.slot[0], sm.slot[1]);
-    do_step(step + 1, sm.slot[1], sm.slot[2]);
-    do_step(step + 2, sm.slot[2], sm.slot[3]);
-    do_step(step + 3, sm.slot[3], sm.slot[0]);
-    csA = __builtin_amdgcn_udot4(pkA, 0x01010101u, csA, false);
-    csB = __builtin_amdgcn_udot4(pkB, 0x01010101u, csB, false);
-    pkA = 0u;
-    pkB = 0u;
+    do_step(sm.slot[0], sm.slot[1]);
+    do_step(sm.slot[1], sm.slot[2]);
+    do_step(sm.slot[2], sm.slot[3]);
+    do_step(sm.slot[3], sm.slot[0]);
+#pragma unroll
+    for (int x = 0; x < SA; ++x) {
+      csA[x] = __builtin_amdgcn_udot4(pkA[x], 0x01010101u, csA[x], false);
+      pkA[x] = 0u;
+    }
+#pragma unroll
+    for (int y = 0; y < SB; ++y) {
+      csB[y] = __builtin_amdgcn_udot4(pkB[y], 0x01010101u, csB[y], false);
+      pkB[y] = 0u;
+    }
   }
   // Drain the DMA of stages past the end before the ring is reused.
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
 
   // Column sums of this unit's rows: lanes l and l + 32 hold partial sums of
   // the same fragment column; combine them in LDS.
-  atomicAdd(&sColA[wm * C::WTM + wn * 32 + (lane & 31)], (int)csA);
-  atomicAdd(&sColB[wn * C::WTN + wm * 32 + (lane & 31)], (int)csB);
+#pragma unroll
+  for (int x = 0; x < SA; ++x) atomicAdd(&sColA[wm * C::WTM + (wn * SA + x) * 32 + (lane & 31)], (int)csA[x]);
+#pragma unroll
+  for (int y = 0; y < SB; ++y) atomicAdd(&sColB[wn * C::WTN + (wm * SB + y) * 32 + (lane & 31)], (int)csB[y]);
   __syncthreads();
 
-  // Split-K: publish partials; the last unit of the tile takes over.
-  if (P.splits > 1) {
+  // Partial unit: publish partials; the unit that completes the tile's row
+  // steps takes over.
+  if (!whole) {
     int32_t* wsn = P.ws_n11 + (int64_t)t * BT * BT;
     int32_t* wsc = P.ws_col + (int64_t)t * 2 * BT;
 #pragma unroll
@@ -368,8 +415,8 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = wm * C::WTM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int col = wn * C::WTN + b * 32 + (lane & 31);
+          const int row = wm * C::WTM + blk_a(a) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int col = wn * C::WTN + blk_b(b) * 32 + (lane & 31);
           const int v = acc[a][b][r];
           if (v) __hip_atomic_fetch_add(&wsn[row * BT + col], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -380,29 +427,39 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (tid == 0) {
-      const int prev = __hip_atomic_fetch_add(&P.counters[t], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      sFlag[0] = (prev == P.splits - 1);
+      const int prev = __hip_atomic_fetch_add(&P.counters[t], nsteps, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      sFlag[0] = (prev + nsteps == P.ksteps);
     }
     __syncthreads();
     if (!sFlag[0]) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // Last arrival: totals back into registers and LDS, then clear the workspace.
+    // Last arrival: totals back into registers and LDS, then clear the
+    // workspace.  The acquire fence orders these plain (cached, coalesced)
+    // loads after every other unit's published adds.
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = wm * C::WTM + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int col = wn * C::WTN + b * 32 + (lane & 31);
-          int32_t* w = &wsn[row * BT + col];
-          acc[a][b][r] = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(w, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int row = wm * C::WTM + blk_a(a) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int col = wn * C::WTN + blk_b(b) * 32 + (lane & 31);
+          acc[a][b][r] = wsn[row * BT + col];
+        }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm * C::WTM + blk_a(a) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+          const int col = wn * C::WTN + blk_b(b) * 32 + (lane & 31);
+          wsn[row * BT + col] = 0;
         }
     __syncthreads();
     for (int c = tid; c < 2 * BT; c += C::NT) {
-      sColA[c] = __hip_atomic_load(&wsc[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&wsc[c], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sColA[c] = wsc[c];
+      wsc[c] = 0;
     }
     if (tid == 0) __hip_atomic_store(&P.counters[t], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
@@ -421,28 +478,65 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int s, const S
       if (i < n) P.colsum_out[i] = sColA[c];
     }
   }
+  // Reciprocals of the marginal counts of both panels' columns (IEEE
+  // division, once per column).
+  float* rA1 = sm.rcp;   // 1 / c_i
+  float* rA0 = rA1 + BT; // 1 / (m - c_i)
+  float* rB1 = rA0 + BT; // 1 / c_j
+  float* rB0 = rB1 + BT; // 1 / (m - c_j)
+  for (int c = tid; c < 2 * BT; c += C::NT) {
+    const int v = sColA[c];  // sColA, then sColB
+    const float r1 = 1.0f / (float)v, r0 = 1.0f / (float)(P.m - v);
+    if (c < BT) {
+      rA1[c] = r1;
+      rA0[c] = r0;
+    } else {
+      rB1[c - BT] = r1;
+      rB0[c - BT] = r0;
+    }
+  }
+  __syncthreads();
+  const float fm = (float)P.m, rfm = 1.0f / fm;
   constexpr int WTN = C::WTN;
   constexpr int STRIP = C::STRIP;
+  static_assert(WTN == 64, "the strip loop gives each lane one column");
   const int ws = wave / C::WAVES_PER_SLOT;  // selects, not an indexed array (keeps it out of memory)
   uint8_t* strip_slot = ws == 0 ? sm.slot[0] : (ws == 1 ? sm.slot[1] : (ws == 2 ? sm.slot[2] : sm.slot[3]));
   int32_t* sN = reinterpret_cast<int32_t*>(strip_slot + (wave % C::WAVES_PER_SLOT) * C::STRIP_BYTES);
   float* sM = reinterpret_cast<float*>(sN + STRIP);
   const int ibase = I * BT + wm * C::WTM;
   const int jbase = J * BT + wn * WTN;
-#pragma unroll
-  for (int a = 0; a < FM; ++a) {
+  // Accumulator block a into the strip.  The strip loop below is not
+  // unrolled (its body, with the FP64 path, is large), so the block is picked
+  // by a switch whose cases index the accumulators with constants: they stay
+  // in registers.
+  auto put_strip = [&](auto A) {
+    constexpr int a = decltype(A)::value;
 #pragma unroll
     for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        sN[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * WTN + b * 32 + (lane & 31)] = acc[a][b][r];
+        sN[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * WTN + blk_b(b) * 32 + (lane & 31)] = acc[a][b][r];
+  };
+  static_assert(FM <= 4, "the strip switch covers four accumulator blocks");
+#pragma clang loop unroll(disable)
+  for (int a = 0; a < FM; ++a) {
+    switch (a) {
+      case 0: put_strip(std::integral_constant<int, 0>{}); break;
+      case 1: if constexpr (FM > 1) put_strip(std::integral_constant<int, (FM > 1 ? 1 : 0)>{}); break;
+      case 2: if constexpr (FM > 2) put_strip(std::integral_constant<int, (FM > 2 ? 2 : 0)>{}); break;
+      default: if constexpr (FM > 3) put_strip(std::integral_constant<int, (FM > 3 ? 3 : 0)>{}); break;
+    }
     __builtin_amdgcn_wave_barrier();
-    const int i0 = ibase + a * 32;
-    for (int e = lane; e < STRIP; e += 64) {
-      const int rr = e / WTN, cc = e % WTN;
-      const int i = i0 + rr, j = jbase + cc;
+    const int i0 = ibase + blk_a(a) * 32;
+    const int jl = wn * WTN + lane, j = jbase + lane;  // this lane's column
+    const int cj = sColB[jl];
+    const float r1j = rB1[jl], r0j = rB0[jl];
+    for (int rr = 0; rr < 32; ++rr) {
+      const int il = i0 - I * BT + rr, i = i0 + rr;  // row, the same for all lanes
+      const int e = rr * WTN + lane;
       const int v11 = sN[e];
-      const float v = mi_value(P.m, sColA[i - I * BT], sColB[j - J * BT], v11, P.epi, P.tau);
+      const float v = mi_value(P.m, fm, rfm, sColA[il], cj, rA1[il], rA0[il], r1j, r0j, v11, P.epi, P.tau);
       sM[e] = v;
       if (i < n && j < n) {
         P.out[i * ln + j] = v;

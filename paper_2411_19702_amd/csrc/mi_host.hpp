@@ -27,14 +27,14 @@ struct DeviceInfo {
 };
 
 struct Plan {
-  int cfg = 0;      // 0: 128 x 128 tiles, 1: 256 x 256 tiles
+  int cfg = 0;          // 0: 128 x 128 tiles, 1: 256 x 256 tiles
   int bt = 128;
-  int ntp = 0;      // column panels
-  int ntiles = 0;   // upper-triangular tiles
-  int splits = 1;   // K splits
-  int kchunk = 0;   // rows per split
-  int tpx = 0;      // tiles per XCD in the plain launch (map 0)
-  int map = 0;      // plain-launch unit-to-XCD mapping (0 tile blocks, 1 K splits)
+  int ntp = 0;          // column panels
+  int ntiles = 0;       // upper-triangular tiles
+  int tpx = 0;          // tiles per XCD in the plain launch
+  int64_t ksteps = 0;   // 64-row steps of a whole tile
+  int splits = 1;       // equal K splits per tile
+  int kchunk = 0;       // rows per split
 };
 
 mi_status device_info(DeviceInfo* out);

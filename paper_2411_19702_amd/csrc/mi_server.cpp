@@ -98,7 +98,7 @@ size_t request_bytes(const mi_problem& p, int64_t ldx) {
   if (p.n > 0) {
     const int cfg = p.tile == MI_TILE_256 ? 1 : 0;
     mi::Plan pl = mi::make_plan(p.m, p.n, p.tile == 0 ? (p.n >= 1536 ? 1 : 0) : cfg, 2);
-    b += mi::workspace_bytes(pl);  // independent of the split count
+    b += mi::workspace_bytes(pl);  // the most any plan of this shape uses
     if (!mi::is_aligned(p.X, ldx)) b += (size_t)p.m * (size_t)mi::packed_pitch(p.n);
   }
   return b;

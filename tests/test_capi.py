@@ -105,11 +105,13 @@ def test_plan_and_tuner_argument_checks(L, tmp_path):
     L.mi_tuner_clear()
     f = tmp_path / "tuned.jsonl"
     assert L.mi_tuner_save(str(f).encode()) == 0
-    f.write_text('{"mb": 40, "nb": 16, "aligned": 1, "tile": 128, "splits": 7, "ms": 1.5}\nnot json\n')
+    f.write_text('{"mb": 40, "nb": 16, "aligned": 1, "tile": 128, "splits": 7, "ms": 1.5}\nnot json\n'
+                 '{"mb": 41, "nb": 16, "aligned": 1, "tile": 96, "splits": 7, "ms": 1.5}\n')
     assert L.mi_tuner_load(str(f).encode()) == 0
     out = tmp_path / "again.jsonl"
     assert L.mi_tuner_save(str(out).encode()) == 0
-    assert '"splits": 7' in out.read_text()
+    text = out.read_text()
+    assert '"splits": 7' in text and '"tile": 96' not in text and text.count("\n") == 1
     L.mi_tuner_clear()
 
 
