@@ -31,7 +31,9 @@ WORKLOADS = {
     "large_1000000x4096": "spec_large",
     "mid_100000x1024": "spec_mid",
     "small_1000x200": "spec_small",
+    "outbound_2000x8192": "spec_outbound",
 }
+OUTPUT_BOUND_ROWS = 2500    # below this m the n^2 FP32 write-back outweighs the Gram (roofline crossover)
 
 
 KERNEL_SOURCES = ("mi_device.hpp", "mi_internal.hpp", "mi_kernels.hip")
@@ -94,6 +96,19 @@ def cpu_baseline(spec, target_s: float):
         "kind": "oracle",
         "sample": f"all {k * (k + 1) // 2} pairs (i <= j) of {k} random columns x all {m} rows of the same matrix; {dt:.2f} s",
     }
+
+
+def roofline(m: int, ldx: int, n: int, kernel_s: float, ops_per_s: float, traffic, tile: int) -> dict:
+    """Roofline object for the fused kernel: against the int8 matrix-core peak,
+    or, for output-bound shapes (m below the crossover), against HBM with the
+    algorithmic bytes (X read once + the n x n FP32 output)."""
+    kern = "mi::k_plain<mi::Cfg<%d, 2, %d, 4>>" % ((128, 2) if tile == 1 else (256, 4))
+    if m < OUTPUT_BOUND_ROWS:
+        gbs = (m * ldx + 4 * n * n) / kernel_s
+        return {"bound": "hbm", "achieved": gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": gbs / PEAK_HBM, "traffic": traffic, "kernel": kern, "kernel_ms": kernel_s * 1e3}
+    return {"bound": "mfma", "achieved": ops_per_s / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TFLOP/s",
+            "frac": ops_per_s / PEAK_INT8_OPS, "traffic": traffic, "kernel": kern, "kernel_ms": kernel_s * 1e3}
 
 
 def _pct(v, q):
@@ -357,23 +372,15 @@ def main() -> int:
             "epilogue": ["fp32", "fp32+fp64-fallback", "fp64"][args.epilogue],
             "tile": [None, 128, 256][tile], "splits": splits,
         },
-        "roofline": {
-            "bound": "mfma",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_INT8_OPS / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_INT8_OPS,
-            "traffic": traffic,
-            "kernel": "mi::k_plain<mi::Cfg<%d, 2, %d, 4>>" % ((128, 2) if tile == 1 else (256, 4)),
-            "kernel_ms": avg_kernel_s * 1e3,
-        },
+        "roofline": roofline(m, X.stride(0), n, avg_kernel_s, achieved, traffic, tile),
     }
     del X
     torch.cuda.empty_cache()
     extras = set() if (args.no_extras or args.shape) else set(args.extras.split(","))
     if "configs" in extras:
         rec["configs"] = [bench_plain(dev, "small_1000x200"), bench_plain(dev, "mid_100000x1024"),
-                          bench_plain(dev, "mid_100000x1024", tune=True)]
+                          bench_plain(dev, "mid_100000x1024", tune=True), bench_plain(dev, "outbound_2000x8192"),
+                          bench_plain(dev, "outbound_2000x8192", tune=True)]
     if "batched" in extras:
         rec["batched"] = bench_batched(dev)
     if "served" in extras:

@@ -96,15 +96,16 @@ struct ProbDev {
 // summed as (t11 + t00) + (t10 + t01).  Contraction into FMAs is disabled so
 // the compiler cannot break that symmetry.
 // ---------------------------------------------------------------------------
-// FP32 cell term n_xy log2(n_xy m / (n_x n_y)), with the reciprocals of the
-// two marginal counts passed in: the ratio is (n_xy m) (r_x r_y), three
-// multiplies and no division.  (r_x r_y) is one commutative multiply, so the
-// term of pair (j, i) is bitwise the one of (i, j).
-__device__ __forceinline__ float cell32(int nxy, float fm, float rx, float ry) {
+// FP32 cell term n_xy log2(n_xy m / (n_x n_y)) from the count and the
+// product a = (m / n_x) (1 / n_y) of the two marginal factors: two
+// multiplies and no division.  A zero count gives 0 (0 log 0 = 0): its ratio
+// is 0 and is raised to FLT_MIN before the log, a finite value that the zero
+// count then cancels.  Factors of zero marginals are stored as 0 (never
+// infinite), and a positive count implies positive marginals.
+__device__ __forceinline__ float cell32(int nxy, float a) {
 #pragma clang fp contract(off)
-  if (nxy <= 0) return 0.0f;                      // 0 log 0 = 0
   const float fn = (float)nxy;
-  return fn * __log2f((fn * fm) * (rx * ry));
+  return fn * __log2f(fmaxf(fn * a, 1.17549435e-38f));
 }
 
 __device__ __forceinline__ double cell64(int nxy, int nx, int ny, int m) {
@@ -125,23 +126,20 @@ __device__ __forceinline__ float mi_value64(int m, int ci, int cj, int n11) {
   return (float)(((d11 + d00) + (d10 + d01)) / (double)m);
 }
 
-// MI of one pair in the requested mode.  r1x = 1 / c_x and r0x = 1 / (m - c_x)
-// (unused where the matching cell count is 0, so 1 / 0 there is harmless);
-// rfm = 1 / m.
-__device__ __forceinline__ float mi_value(int m, float fm, float rfm, int ci, int cj, float r1i, float r0i,
-                                          float r1j, float r0j, int n11, int epi, float tau) {
+// FP32 MI of one pair (Eq. 2 / 3).  a1i = m / c_i and a0i = m / (m - c_i)
+// for the row variable, r1j = 1 / c_j and r0j = 1 / (m - c_j) for the column
+// variable (0 where the marginal count is 0); rfm = 1 / m.
+__device__ __forceinline__ float mi_value32(int m, int ci, int cj, int n11, float a1i, float a0i, float r1j,
+                                            float r0j, float rfm) {
 #pragma clang fp contract(off)
-  if (epi == 2) return mi_value64(m, ci, cj, n11);
   const int n10 = ci - n11;         // X_i = 1, X_j = 0
   const int n01 = cj - n11;         // X_i = 0, X_j = 1
   const int n00 = (m - ci) - n01;   // = m - c_i - c_j + n11, without overflow
-  const float t11 = cell32(n11, fm, r1i, r1j);
-  const float t00 = cell32(n00, fm, r0i, r0j);
-  const float t10 = cell32(n10, fm, r1i, r0j);
-  const float t01 = cell32(n01, fm, r0i, r1j);
-  const float v = ((t11 + t00) + (t10 + t01)) * rfm;
-  if (epi == 1 && v < tau) return mi_value64(m, ci, cj, n11);
-  return v;
+  const float t11 = cell32(n11, a1i * r1j);
+  const float t00 = cell32(n00, a0i * r0j);
+  const float t10 = cell32(n10, a1i * r0j);
+  const float t01 = cell32(n01, a0i * r1j);
+  return ((t11 + t00) + (t10 + t01)) * rfm;
 }
 
 // ---------------------------------------------------------------------------
@@ -478,25 +476,26 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       if (i < n) P.colsum_out[i] = sColA[c];
     }
   }
-  // Reciprocals of the marginal counts of both panels' columns (IEEE
-  // division, once per column).
-  float* rA1 = sm.rcp;   // 1 / c_i
-  float* rA0 = rA1 + BT; // 1 / (m - c_i)
-  float* rB1 = rA0 + BT; // 1 / c_j
-  float* rB0 = rB1 + BT; // 1 / (m - c_j)
+  // Marginal factors of both panels' columns (IEEE division, once per
+  // column): m / c and m / (m - c) for the rows' variables (panel I), 1 / c
+  // and 1 / (m - c) for the columns' (panel J); 0 where the count is 0.
+  const float fm = (float)P.m, rfm = 1.0f / fm;
+  float* rA1 = sm.rcp;    // m / c_i
+  float* rA0 = rA1 + BT;  // m / (m - c_i)
+  float* rB1 = rA0 + BT;  // 1 / c_j
+  float* rB0 = rB1 + BT;  // 1 / (m - c_j)
   for (int c = tid; c < 2 * BT; c += C::NT) {
     const int v = sColA[c];  // sColA, then sColB
-    const float r1 = 1.0f / (float)v, r0 = 1.0f / (float)(P.m - v);
+    const int w = P.m - v;
     if (c < BT) {
-      rA1[c] = r1;
-      rA0[c] = r0;
+      rA1[c] = v > 0 ? fm / (float)v : 0.0f;
+      rA0[c] = w > 0 ? fm / (float)w : 0.0f;
     } else {
-      rB1[c - BT] = r1;
-      rB0[c - BT] = r0;
+      rB1[c - BT] = v > 0 ? 1.0f / (float)v : 0.0f;
+      rB0[c - BT] = w > 0 ? 1.0f / (float)w : 0.0f;
     }
   }
   __syncthreads();
-  const float fm = (float)P.m, rfm = 1.0f / fm;
   constexpr int WTN = C::WTN;
   constexpr int STRIP = C::STRIP;
   static_assert(WTN == 64, "the strip loop gives each lane one column");
@@ -506,6 +505,9 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   float* sM = reinterpret_cast<float*>(sN + STRIP);
   const int ibase = I * BT + wm * C::WTM;
   const int jbase = J * BT + wn * WTN;
+  const int jl = wn * WTN + lane, j = jbase + lane;  // this lane's column
+  const int cj = sColB[jl];
+  const float r1j = rB1[jl], r0j = rB0[jl];
   // Accumulator block a into the strip.  The strip loop below is not
   // unrolled (its body, with the FP64 path, is large), so the block is picked
   // by a switch whose cases index the accumulators with constants: they stay
@@ -518,6 +520,32 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       for (int r = 0; r < 16; ++r)
         sN[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * WTN + blk_b(b) * 32 + (lane & 31)] = acc[a][b][r];
   };
+  // MI of the strip's rows, one column per lane, written as tile rows
+  // (consecutive lanes, consecutive j).  The epilogue mode is a template
+  // argument, so the FP32 loop carries no per-element mode tests.  In a
+  // diagonal tile only i <= j is stored; the mirror pass fills i > j, so the
+  // output is bitwise symmetric by construction.
+  auto strip_rows = [&](int i0, auto EPI) {
+    constexpr int epi = decltype(EPI)::value;
+    for (int rr = 0; rr < 32; ++rr) {
+      const int il = i0 - I * BT + rr, i = i0 + rr;  // row, the same for all lanes
+      const int e = rr * WTN + lane;
+      const int v11 = sN[e];
+      const int ci = sColA[il];
+      float v;
+      if (epi == 2) {
+        v = mi_value64(P.m, ci, cj, v11);
+      } else {
+        v = mi_value32(P.m, ci, cj, v11, rA1[il], rA0[il], r1j, r0j, rfm);
+        if (epi == 1 && v < P.tau) v = mi_value64(P.m, ci, cj, v11);
+      }
+      sM[e] = v;
+      if (i < n && j < n && (!diag || j >= i)) {
+        P.out[i * ln + j] = v;
+        if (P.n11_out) P.n11_out[i * ln + j] = v11;
+      }
+    }
+  };
   static_assert(FM <= 4, "the strip switch covers four accumulator blocks");
 #pragma clang loop unroll(disable)
   for (int a = 0; a < FM; ++a) {
@@ -529,29 +557,19 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     }
     __builtin_amdgcn_wave_barrier();
     const int i0 = ibase + blk_a(a) * 32;
-    const int jl = wn * WTN + lane, j = jbase + lane;  // this lane's column
-    const int cj = sColB[jl];
-    const float r1j = rB1[jl], r0j = rB0[jl];
-    for (int rr = 0; rr < 32; ++rr) {
-      const int il = i0 - I * BT + rr, i = i0 + rr;  // row, the same for all lanes
-      const int e = rr * WTN + lane;
-      const int v11 = sN[e];
-      const float v = mi_value(P.m, fm, rfm, sColA[il], cj, rA1[il], rA0[il], r1j, r0j, v11, P.epi, P.tau);
-      sM[e] = v;
-      if (i < n && j < n) {
-        P.out[i * ln + j] = v;
-        if (P.n11_out) P.n11_out[i * ln + j] = v11;
-      }
+    switch (P.epi) {
+      case 0: strip_rows(i0, std::integral_constant<int, 0>{}); break;
+      case 1: strip_rows(i0, std::integral_constant<int, 1>{}); break;
+      default: strip_rows(i0, std::integral_constant<int, 2>{}); break;
     }
     __builtin_amdgcn_wave_barrier();
-    if (!diag) {
-      for (int e = lane; e < STRIP; e += 64) {
-        const int cc = e / 32, rr = e % 32;
-        const int i = i0 + rr, j = jbase + cc;
-        if (i < n && j < n) {
-          P.out[j * ln + i] = sM[rr * WTN + cc];
-          if (P.n11_out) P.n11_out[j * ln + i] = sN[rr * WTN + cc];
-        }
+    // Mirror rows (consecutive lanes, consecutive i).
+    for (int e = lane; e < STRIP; e += 64) {
+      const int cc = e / 32, rr = e % 32;
+      const int i = i0 + rr, jm = jbase + cc;
+      if (i < n && jm < n && (!diag || jm > i)) {
+        P.out[jm * ln + i] = sM[rr * WTN + cc];
+        if (P.n11_out) P.n11_out[jm * ln + i] = sN[rr * WTN + cc];
       }
     }
     __builtin_amdgcn_wave_barrier();

@@ -232,6 +232,15 @@ def spec_large(seed: int = SEED0 + 2, m: int = 1_000_000, n: int = 4096) -> Data
     return DatasetSpec(m=m, n=n, seed=seed, p=p, name=f"large_{m}x{n}")
 
 
+def spec_outbound(seed: int = SEED0 + 5, m: int = 2000, n: int = 8192) -> DatasetSpec:
+    """2,000 x 8,192 (few rows, many columns: the n x n FP32 output, 268 MB,
+    outweighs the 16 MB input); p_j ~ U[0.01, 0.5]; floor(1% n) planted pairs."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0.01, 0.5, size=n)
+    planted = _pick_planted(rng, n, n // 100, 0.3, set())
+    return DatasetSpec(m=m, n=n, seed=seed, p=p, planted=planted, name=f"outbound_{m}x{n}")
+
+
 def _log_uniform_int(rng: np.random.Generator, lo: int, hi: int) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
 

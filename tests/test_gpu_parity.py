@@ -186,3 +186,18 @@ def test_large_workload_sampled(epi):
     Xs = synth.columns(spec, cols).numpy()
     err = compare_columns(Xs, cols, out, n11, cs)
     say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
+
+
+@pytest.mark.parametrize("tile", [0, 1])
+def test_output_bound_workload_sampled(tile):
+    """2,000 x 8,192: few rows, many tiles (the write-back dominates)."""
+    spec = synth.spec_outbound()
+    say(f"[parity] outbound 2000x8192 tile={tile}")
+    X = _gen(spec)
+    out, n11, cs = run_gpu(X, tile=tile)
+    rng = np.random.default_rng(4)
+    cols = sorted(set(rng.choice(spec.n, size=40, replace=False).tolist())
+                  | {0, 255, 256, 4095, 4096, spec.n - 1} | {d for d, _s, _q in spec.planted[:4]})
+    Xs = synth.columns(spec, cols).numpy()
+    err = compare_columns(Xs, cols, out, n11, cs)
+    say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
