@@ -527,7 +527,8 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   // output is bitwise symmetric by construction.
   auto strip_rows = [&](int i0, auto EPI) {
     constexpr int epi = decltype(EPI)::value;
-    for (int rr = 0; rr < 32; ++rr) {
+    const int rows = min(32, n - i0);  // rows past n (tile padding) are skipped
+    for (int rr = 0; rr < rows; ++rr) {
       const int il = i0 - I * BT + rr, i = i0 + rr;  // row, the same for all lanes
       const int e = rr * WTN + lane;
       const int v11 = sN[e];
@@ -547,8 +548,10 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     }
   };
   static_assert(FM <= 4, "the strip switch covers four accumulator blocks");
+  // A wave whose columns all lie past n (tile padding) has nothing to write.
+  const int nstrips = jbase < n ? FM : 0;
 #pragma clang loop unroll(disable)
-  for (int a = 0; a < FM; ++a) {
+  for (int a = 0; a < nstrips; ++a) {
     switch (a) {
       case 0: put_strip(std::integral_constant<int, 0>{}); break;
       case 1: if constexpr (FM > 1) put_strip(std::integral_constant<int, (FM > 1 ? 1 : 0)>{}); break;
@@ -557,6 +560,10 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     }
     __builtin_amdgcn_wave_barrier();
     const int i0 = ibase + blk_a(a) * 32;
+    if (i0 >= n) {  // strip rows all past n: skip (uniform)
+      __builtin_amdgcn_wave_barrier();
+      continue;
+    }
     switch (P.epi) {
       case 0: strip_rows(i0, std::integral_constant<int, 0>{}); break;
       case 1: strip_rows(i0, std::integral_constant<int, 1>{}); break;

@@ -16,6 +16,17 @@ struct UnitRef {
   int32_t pad;
 };
 
+// One layout to repack into a 16-byte pitch (Y is m x ldy, ldy % 16 == 0).
+struct RepackDesc {
+  const uint8_t* X;
+  int64_t ldx;
+  uint8_t* Y;
+  int64_t ldy;
+  int64_t m, n;
+  int64_t first_block;  // batched launch: first block of this layout
+  int64_t blocks;       // blocks that work on this layout
+};
+
 // Tile configurations: 0 = 128 x 128 (Cfg128), 1 = 256 x 256 (Cfg256).
 constexpr int kNumCfg = 2;
 int cfg_tile(int cfg);
@@ -27,6 +38,8 @@ hipError_t launch_persistent(int cfg, const ProbDev* probs, const UnitRef* units
 hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st);
 hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Y, int64_t ldy,
                          hipStream_t st);
+hipError_t launch_repack_batch(const RepackDesc* descs, int count, int64_t blocks, hipStream_t st);
+int64_t repack_blocks(int64_t m, int64_t ldy);
 hipError_t fill_i32(int* p, int v, int count, hipStream_t st);
 int occupancy(int cfg);
 int persistent_occupancy(int cfg);

@@ -73,21 +73,59 @@ __global__ void k_validate(const uint8_t* __restrict__ X, int64_t m, int64_t n, 
 
 // Y[r][c] = X[r][c] for c < n, 0 for n <= c < ldy: a 16-byte aligned copy with
 // pitch ldy (a multiple of 16) for layouts the DMA path cannot read directly.
-__global__ void k_repack(const uint8_t* __restrict__ X, int64_t m, int64_t n, int64_t ldx, uint8_t* __restrict__ Y,
-                         int64_t ldy) {
-  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
-    const uint8_t* src = X + row * ldx;
-    uint32_t* dst = reinterpret_cast<uint32_t*>(Y + row * ldy);
-    for (int64_t w = threadIdx.x; w < ldy / 4; w += blockDim.x) {
+// Repack of a layout the DMA path cannot read (base or pitch not a multiple of
+// 16 bytes) into a 16-byte pitch.  One thread writes one 16-byte chunk of Y:
+// columns [c, c + 16) of one row, zeros past n.  Inside X it reads the five
+// aligned dwords around the chunk and shifts them into place; chunks whose
+// window would reach outside [X, last valid byte] read byte by byte.
+__device__ __forceinline__ void repack_chunk(const RepackDesc& d, int64_t q) {
+  const int64_t segs = d.ldy >> 4;
+  const int64_t row = q / segs;
+  const int64_t c = (q - row * segs) * 16;
+  const uint8_t* src = d.X + row * d.ldx + c;
+  const uint8_t* lo = reinterpret_cast<const uint8_t*>(reinterpret_cast<uintptr_t>(src) & ~(uintptr_t)3);
+  const uint8_t* end = d.X + (d.m - 1) * d.ldx + d.n;  // one past the last byte of X that is read
+  uint32_t w[4];
+  if (c + 16 <= d.n && lo >= d.X && lo + 20 <= end) {
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lo);
+    const uint32_t a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3], a4 = p[4];
+    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(src) & 3);
+    w[0] = __builtin_amdgcn_alignbyte(a1, a0, sh);
+    w[1] = __builtin_amdgcn_alignbyte(a2, a1, sh);
+    w[2] = __builtin_amdgcn_alignbyte(a3, a2, sh);
+    w[3] = __builtin_amdgcn_alignbyte(a4, a3, sh);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
       uint32_t v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int64_t c = 4 * w + b;
-        if (c < n) v |= (uint32_t)src[c] << (8 * b);
-      }
-      dst[w] = v;
+      for (int b = 0; b < 4; ++b)
+        if (c + 4 * k + b < d.n) v |= (uint32_t)src[4 * k + b] << (8 * b);
+      w[k] = v;
     }
   }
+  *reinterpret_cast<uint4*>(d.Y + row * d.ldy + c) = uint4{w[0], w[1], w[2], w[3]};
+}
+
+__global__ __launch_bounds__(256) void k_repack(RepackDesc d) {
+  const int64_t total = d.m * (d.ldy >> 4);
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256)
+    repack_chunk(d, q);
+}
+
+// All repacks of a batch in one launch: block b belongs to the dataset whose
+// block range [first_block, first_block + blocks) holds it.
+__global__ __launch_bounds__(256) void k_repack_batch(const RepackDesc* __restrict__ descs, int count) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // uniform: every lane searches the same block index
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].first_block <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const RepackDesc d = descs[lo];
+  const int64_t total = d.m * (d.ldy >> 4);
+  for (int64_t q = (b - d.first_block) * 256 + threadIdx.x; q < total; q += d.blocks * 256) repack_chunk(d, q);
 }
 
 template <class C>
@@ -120,10 +158,24 @@ hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, 
   return hipGetLastError();
 }
 
+// Blocks for one layout: one 16-byte chunk per thread, at most 65536 blocks
+// (larger layouts loop).
+int64_t repack_blocks(int64_t m, int64_t ldy) {
+  const int64_t b = (m * (ldy >> 4) + 255) / 256;
+  return b < 65536 ? (b > 0 ? b : 1) : 65536;
+}
+
 hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Y, int64_t ldy,
                          hipStream_t st) {
-  const int64_t blocks = m < 8192 ? m : 8192;
-  hipLaunchKernelGGL(k_repack, dim3((unsigned)blocks), dim3(256), 0, st, X, m, n, ldx, Y, ldy);
+  const int64_t blocks = repack_blocks(m, ldy);
+  RepackDesc d{X, ldx, Y, ldy, m, n, 0, blocks};
+  hipLaunchKernelGGL(k_repack, dim3((unsigned)blocks), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_repack_batch(const RepackDesc* descs, int count, int64_t blocks, hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_repack_batch, dim3((unsigned)blocks), dim3(256), 0, st, descs, count);
   return hipGetLastError();
 }
 
