@@ -187,7 +187,7 @@ def bench_batched(dev, reps: int = 3):
     return res
 
 
-def bench_served(dev, count: int = 300, loads=(0.5, 0.8, 0.95, 1.5)):
+def bench_served(dev, count: int = 300, loads=(0.5, 0.8, 0.95, 1.5), slots: int = 3):
     """Poisson arrivals of MI requests (m log-uniform [1k, 200k], n log-uniform
     [128, 8192], densities U[0.005, 0.5]): the continuous-batching server vs
     one-at-a-time plain solves, both replayed at lambda = load * mu for each
@@ -223,8 +223,8 @@ def bench_served(dev, count: int = 300, loads=(0.5, 0.8, 0.95, 1.5)):
 
     res = {"workload": f"served: {count} Poisson requests, m log-uniform [1000, 200000], "
                        f"n log-uniform [128, 8192], densities U[0.005, 0.5]",
-           "mu_req_per_s": mu, "budget_bytes": budget, "loads": []}
-    with mi.Server(hbm_budget_bytes=budget, max_slots=4) as srv:
+           "mu_req_per_s": mu, "budget_bytes": budget, "server_slots": slots, "loads": []}
+    with mi.Server(hbm_budget_bytes=budget, max_slots=slots) as srv:
         for t in [srv.submit(X, o) for X, o in zip(Xs, outs)]:      # warm the server's streams
             srv.wait(t, timeout_s=300)
         for load in loads:
@@ -284,6 +284,7 @@ def main() -> int:
     ap.add_argument("--extras", default="configs,batched,served",
                     help="comma list of extra measurements: configs (the 1000 x 200 and 100000 x 1024 "
                          "workloads), batched (256 datasets), served (Poisson request trace)")
+    ap.add_argument("--served-slots", type=int, default=3, help="server slots (streams) in the served measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB per step "
                          "(reference for the HBM byte counters)")
@@ -384,7 +385,7 @@ def main() -> int:
     if "batched" in extras:
         rec["batched"] = bench_batched(dev)
     if "served" in extras:
-        rec["served"] = bench_served(dev)
+        rec["served"] = bench_served(dev, slots=args.served_slots)
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

@@ -7,17 +7,19 @@
  * Clients submit requests whose data already lives on the device; the server
  *   - admits waiting requests in arrival order while a slot is free and the
  *     memory of everything in flight stays within the HBM budget,
- *   - launches the requests admitted together as one batch (one persistent
- *     launch pulling work units of all of them; a lone request runs as a
- *     plain launch) on a free slot, so work of newly admitted requests runs
- *     on the device next to requests that are still running,
+ *   - launches the requests admitted together as one batch on a free slot:
+ *     a few small requests as plain launches back to back, many as one
+ *     persistent launch pulling work units of all of them, a large request
+ *     alone, so work of newly admitted requests runs on the device next to
+ *     requests that are still running,
  *   - sizes batches by an estimate of each request's device time: a large
- *     request (about 250 us or more alone) runs by itself and only one large
- *     request runs at a time, small requests are grouped up to about 400 us
- *     of summed work and run on the other slots (they may start before a
- *     large request that waits for the running one; a request that waits
- *     for budget is never overtaken),
- *   - detects completion with events and records each request's latency from
+ *     request (about 250 us or more alone) runs by itself; with two or more
+ *     slots, slot 0 runs large requests one at a time and the other slots
+ *     run batches of small requests (up to about 400 us of summed work);
+ *     small requests may start before a large request that waits for slot
+ *     0, but a request that waits for budget is never overtaken,
+ *   - detects completion with events (per request for plain launches, per
+ *     batch for a persistent launch) and records each request's latency from
  *     submission to completion.
  * A request's results are bitwise the same whether it runs alone or in a
  * batch (counts are exact integers and MI is a pure function of them).

@@ -3,22 +3,25 @@
 // One host thread per server.  Requests wait in a FIFO; whenever a slot (a
 // HIP stream) is free the loop admits waiting requests that fit the HBM
 // budget next to what is already running and launches them on that slot.
-// Batches on different slots run concurrently on the device.  Completion is
-// detected by polling one event per batch.
+// Batches on different slots run concurrently on the device.
 //
 // Batch formation uses a cost estimate per request (pair updates at a
 // sustained rate plus a launch floor), so that small requests are never tied
 // to a large one:
 //   - a large request (estimate >= kLargeUs) runs alone, as a plain launch;
-//   - consecutive small requests are launched together, as one persistent
-//     launch, until their summed estimate reaches kBatchCapUs;
-//   - one large request runs at a time (alone it already fills the device;
-//     two at once only share it and both finish later), first come first
-//     served among large requests; small requests use the other slots, and
-//     while the head of the queue is a large request that has to wait for
-//     the running one, small requests behind it may start first.
+//   - consecutive small requests are launched together until their summed
+//     estimate reaches kBatchCapUs: up to kPlainBatch of them as plain
+//     launches back to back, each completing on its own event, more as one
+//     persistent launch that completes as a whole;
+//   - with two or more slots, slot 0 runs the large requests, one at a time
+//     and first come first served (alone a large request already fills the
+//     device; two at once only share it), and the other slots run the small
+//     batches; while the head of the queue is a large request waiting for
+//     slot 0, small requests behind it may start first.
 // Admission against the budget stays first come, first served: a request
 // that does not fit waits, and nothing behind it overtakes it.
+// While work is in flight the loop polls its events, yielding the CPU between
+// polls (a timed wait would oversleep by tens of microseconds).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,15 +53,21 @@ struct Req {
   mi_status status = MI_OK;
 };
 
+// Requests launched together on one slot.  A batch of plain launches has one
+// event per request (each completes on its own, in stream order); a
+// persistent batch has one event for all.
 struct Batch {
   std::vector<uint64_t> tickets;
-  hipEvent_t ev = nullptr;
+  std::vector<size_t> req_bytes;
+  std::vector<hipEvent_t> evs;
+  size_t ndone = 0;
   int slot = -1;
   size_t bytes = 0;
   bool large = false;
 };
 
 constexpr int kMaxBatch = 256;          // requests launched together at most
+constexpr int kPlainBatch = 8;          // batches up to this size run as plain launches
 constexpr double kLargeUs = 250.0;      // estimate from which a request runs alone
 constexpr double kBatchCapUs = 400.0;   // summed estimate of one batch of small requests
 
@@ -85,7 +94,8 @@ struct mi_server {
   std::thread th;
 
   void loop();
-  void finish_batch(Batch& b, mi_status st, Clock::time_point now);
+  void finish_ticket(Batch& b, size_t k, mi_status st, Clock::time_point now);
+  void release_batch(Batch& b);
 };
 
 namespace {
@@ -116,20 +126,22 @@ double estimate_us(const mi_problem& p) {
 
 }  // namespace
 
-void mi_server::finish_batch(Batch& b, mi_status st, Clock::time_point now) {
-  for (uint64_t t : b.tickets) {
-    auto it = reqs.find(t);
-    if (it == reqs.end()) continue;
+void mi_server::finish_ticket(Batch& b, size_t k, mi_status st, Clock::time_point now) {
+  auto it = reqs.find(b.tickets[k]);
+  if (it != reqs.end()) {
     it->second.state = kDone;
     it->second.status = st;
     it->second.t_done = now;
-    stats.completed++;
   }
-  in_flight -= b.bytes;
+  stats.completed++;
+  in_flight -= b.req_bytes[k];
   stats.bytes_in_flight = in_flight;
+}
+
+void mi_server::release_batch(Batch& b) {
   slot_busy[b.slot] = 0;
-  if (b.ev) free_events.push_back(b.ev);
-  b.ev = nullptr;
+  for (hipEvent_t ev : b.evs) free_events.push_back(ev);
+  b.evs.clear();
 }
 
 void mi_server::loop() {
@@ -137,33 +149,47 @@ void mi_server::loop() {
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     bool progressed = false;
-    // 1. Completed batches.
+    // 1. Completed requests (in stream order within a batch).
     const auto now = Clock::now();
     for (size_t i = 0; i < running.size();) {
-      hipError_t e = hipEventQuery(running[i].ev);
-      if (e == hipErrorNotReady) {
-        ++i;
-        continue;
+      Batch& b = running[i];
+      const bool one_event = b.evs.size() == 1 && b.tickets.size() > 1;
+      while (b.ndone < b.tickets.size()) {
+        const hipError_t e = hipEventQuery(one_event ? b.evs[0] : b.evs[b.ndone]);
+        if (e == hipErrorNotReady) break;
+        const mi_status st = e == hipSuccess ? MI_OK : MI_ERR_DEVICE;
+        if (one_event) {
+          for (size_t k = b.ndone; k < b.tickets.size(); ++k) finish_ticket(b, k, st, now);
+          b.ndone = b.tickets.size();
+        } else {
+          finish_ticket(b, b.ndone++, st, now);
+        }
+        progressed = true;
       }
-      finish_batch(running[i], e == hipSuccess ? MI_OK : MI_ERR_DEVICE, now);
-      running.erase(running.begin() + i);
-      progressed = true;
+      if (b.ndone == b.tickets.size()) {
+        release_batch(b);
+        running.erase(running.begin() + i);
+      } else {
+        ++i;
+      }
     }
     if (progressed) cv_done.notify_all();
 
     // 2. Admission onto one free slot (see the policy at the top of this file).
-    int slot = -1, large_running = 0;
-    for (int s = 0; s < nslots; ++s)
-      if (!slot_busy[s] && slot < 0) slot = s;
-    for (const auto& rb : running) large_running += rb.large ? 1 : 0;
-    if (slot >= 0 && !waiting.empty()) {
+    // With two or more slots, slot 0 runs large requests and the others
+    // batches of small ones; with one slot it runs both.
+    const bool split = nslots >= 2;
+    int small_slot = -1;
+    for (int s = split ? 1 : 0; s < nslots && small_slot < 0; ++s)
+      if (!slot_busy[s]) small_slot = s;
+    const bool large_free = !slot_busy[0];
+    if (!waiting.empty() && (large_free || small_slot >= 0)) {
       Batch b;
-      b.slot = slot;
       std::vector<mi_problem> probs;
-      const bool large_ok = large_running == 0;
       auto take = [&](std::deque<uint64_t>::iterator it) {
         Req& r = reqs[*it];
         b.bytes += r.bytes;
+        b.req_bytes.push_back(r.bytes);
         b.tickets.push_back(*it);
         probs.push_back(r.p);
         r.state = kRunning;
@@ -171,17 +197,20 @@ void mi_server::loop() {
       };
       auto it = waiting.begin();
       const Req& head = reqs[*it];
-      if (head.est_us >= kLargeUs && large_ok) {
-        if (in_flight + head.bytes <= budget) {
+      const bool head_large = head.est_us >= kLargeUs;
+      if (head_large && large_free) {
+        if (in_flight + head.bytes <= budget) {  // else it waits for budget, and nothing overtakes it
           take(it);
           b.large = true;
+          b.slot = 0;
         }
-      } else {
-        // Small requests from the head on; a large head without a slot is
-        // passed over, any other request that is large or over budget ends
-        // the batch.
+      } else if (small_slot >= 0 && (!head_large || split)) {
+        // Small requests from the head on; a large head waiting for its slot
+        // is passed over, any other request that is large or over budget
+        // ends the batch.
+        b.slot = small_slot;
         double cost = 0.0;
-        if (head.est_us >= kLargeUs) ++it;
+        if (head_large) ++it;
         while (it != waiting.end() && (int)probs.size() < kMaxBatch) {
           const Req& r = reqs[*it];
           if (r.est_us >= kLargeUs) break;
@@ -192,6 +221,7 @@ void mi_server::loop() {
         }
       }
       if (!probs.empty()) {
+        const int slot = b.slot;
         slot_busy[slot] = 1;
         in_flight += b.bytes;
         stats.bytes_in_flight = in_flight;
@@ -200,27 +230,49 @@ void mi_server::loop() {
         for (auto& rb : running) nrun += rb.tickets.size();
         stats.max_in_flight = std::max<uint64_t>(stats.max_in_flight, nrun + probs.size());
         stats.batches++;
-        if (free_events.empty()) {
+        // A few requests run as plain launches back to back on the slot's
+        // stream (no work-list upload), each with its own completion event;
+        // more run as one persistent launch.
+        const bool plain = (int)probs.size() <= kPlainBatch;
+        const size_t nev = plain ? probs.size() : 1;
+        mi_status rc = MI_OK;
+        while (free_events.size() < nev && rc == MI_OK) {
           hipEvent_t ev = nullptr;
-          if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) free_events.push_back(ev);
+          if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess)
+            free_events.push_back(ev);
+          else
+            rc = MI_ERR_DEVICE;
+        }
+        for (size_t q = 0; q < nev && rc == MI_OK; ++q) {
+          b.evs.push_back(free_events.back());
+          free_events.pop_back();
         }
         hipStream_t st = streams[slot];
+        size_t launched = 0;  // requests whose launch and event were issued
         lk.unlock();  // launches may allocate; clients can keep submitting
-        mi_status rc = probs.size() == 1 ? mi::run_one(&probs[0], st, 0)
-                                         : mi::run_batched(probs.data(), (int64_t)probs.size(), st, MI_BATCH_PERSISTENT);
-        lk.lock();
-        if (rc == MI_OK && !free_events.empty()) {
-          b.ev = free_events.back();
-          free_events.pop_back();
-          if (hipEventRecord(b.ev, st) != hipSuccess) rc = MI_ERR_DEVICE;
-        } else if (rc == MI_OK) {
-          rc = MI_ERR_DEVICE;
-        }
         if (rc == MI_OK) {
-          running.push_back(b);
+          if (plain) {
+            for (; launched < probs.size(); ++launched) {
+              rc = mi::run_one(&probs[launched], st, 0);
+              if (rc == MI_OK && hipEventRecord(b.evs[launched], st) != hipSuccess) rc = MI_ERR_DEVICE;
+              if (rc != MI_OK) break;
+            }
+          } else {
+            rc = mi::run_batched(probs.data(), (int64_t)probs.size(), st, MI_BATCH_PERSISTENT);
+            if (rc == MI_OK && hipEventRecord(b.evs[0], st) != hipSuccess) rc = MI_ERR_DEVICE;
+            if (rc == MI_OK) launched = probs.size();
+          }
+        }
+        lk.lock();
+        if (rc == MI_OK) {
+          running.push_back(std::move(b));
         } else {
+          // Requests launched before the failure complete normally; the
+          // failed one and those after it report the error.
           (void)hipStreamSynchronize(st);
-          finish_batch(b, rc, Clock::now());
+          const auto t = Clock::now();
+          for (size_t k = 0; k < b.tickets.size(); ++k) finish_ticket(b, k, k < launched ? MI_OK : rc, t);
+          release_batch(b);
           cv_done.notify_all();
         }
         progressed = true;
@@ -229,10 +281,15 @@ void mi_server::loop() {
 
     if (stop && waiting.empty() && running.empty()) break;
     if (!progressed) {
-      if (running.empty())
+      if (running.empty()) {
         cv_work.wait_for(lk, std::chrono::milliseconds(2));
-      else
-        cv_work.wait_for(lk, std::chrono::microseconds(20));
+      } else {
+        // Work in flight: poll its events again soon.  A timed wait can
+        // oversleep by tens of microseconds, so release the lock and yield.
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+      }
     }
   }
 }
