@@ -160,6 +160,46 @@ def bench_plain(dev, workload: str, steps: int = 30, tune: bool = False):
             "hbm_algorithmic_GBps": nbytes / k / 1e9, "frac_hbm_peak": nbytes / k / PEAK_HBM}
 
 
+def bench_sparse(dev, thr: float = 0.01, reps: int = 3):
+    """Sparse threshold output on the wide 20,000 x 32,768 workload: only the
+    pairs with MI >= thr are written, against the dense 4.3 GB matrix."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    spec = synth.spec_wide()
+    X = synth.generate(spec, device=dev)
+    m, n = spec.m, spec.n
+    cap = 4 * n
+    pairs = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+    count = torch.empty((1,), dtype=torch.int64, device=dev)
+    prob_sparse = mi.make_problem(X, None, pairs=pairs, pairs_count=count, pairs_threshold=thr)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    import ctypes
+    t_sparse = timed(lambda: mi._check(mi.lib().mi_all_pairs_ex(ctypes.byref(prob_sparse), mi._stream_handle(stream))))
+    found = int(count.item())
+    out = torch.empty((n, n), dtype=torch.float32, device=dev)
+    t_dense = timed(lambda: mi.mi_all_pairs_ex(X, out=out, stream=stream))
+    dense_count = int(torch.triu(out >= thr, diagonal=1).sum().item())
+    del out
+    torch.cuda.empty_cache()
+    pu = m * n * (n + 1) / 2
+    return {"workload": f"wide_{m}x{n}", "threshold_bits": thr, "pairs_found": found,
+            "pairs_in_dense_filter": dense_count, "sparse_ms": t_sparse * 1e3, "dense_ms": t_dense * 1e3,
+            "sparse_pair_updates_per_s": pu / t_sparse, "dense_output_bytes": 4 * n * n,
+            "sparse_output_bytes": 12 * min(found, cap)}
+
+
 def bench_batched(dev, reps: int = 3):
     """256 independent datasets: one persistent launch vs a replayed hipGraph
     of plain launches vs 256 sequential plain calls (same results, bitwise)."""
@@ -281,9 +321,10 @@ def main() -> int:
     ap.add_argument("--tile", type=int, default=0, help="force a tile config (1: 128, 2: 256)")
     ap.add_argument("--splits", type=int, default=0, help="force the K-split count")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra measurements")
-    ap.add_argument("--extras", default="configs,batched,served",
+    ap.add_argument("--extras", default="configs,batched,served,sparse",
                     help="comma list of extra measurements: configs (the 1000 x 200 and 100000 x 1024 "
-                         "workloads), batched (256 datasets), served (Poisson request trace)")
+                         "workloads), batched (256 datasets), served (Poisson request trace), sparse (threshold "
+                         "output on 20000 x 32768)")
     ap.add_argument("--served-slots", type=int, default=3, help="server slots (streams) in the served measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB per step "
@@ -386,6 +427,8 @@ def main() -> int:
         rec["batched"] = bench_batched(dev)
     if "served" in extras:
         rec["served"] = bench_served(dev, slots=args.served_slots)
+    if "sparse" in extras:
+        rec["sparse"] = bench_sparse(dev)
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

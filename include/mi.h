@@ -75,12 +75,19 @@ typedef enum mi_tile {
   MI_TILE_256 = 2   /* 256 x 256 output tile, 8 waves of 128 x 64 */
 } mi_tile;
 
+/* One entry of the sparse (threshold) output: MI(X_i; X_j) in bits, i < j. */
+typedef struct mi_pair {
+  int32_t i, j;
+  float mi;
+} mi_pair;
+
 typedef struct mi_problem {
   const uint8_t* X;      /* device, m x ldx bytes, row-major, 0/1                   */
   int64_t m;             /* rows (samples), >= 1                                    */
   int64_t n;             /* columns (variables), >= 0                               */
   int64_t ldx;           /* row pitch in bytes, >= n; 0 means n                     */
-  float* out;            /* device, n x n FP32 row-major (required when n > 0)      */
+  float* out;            /* device, n x n FP32 row-major; may be NULL when `pairs`  */
+                         /* is given (then no dense matrix is written)              */
   int32_t* n11_out;      /* optional device n x n int32: the 1-1 counts X^T X        */
   int32_t* colsum_out;   /* optional device int32[n]: column sums c                 */
   int32_t epilogue;      /* mi_epilogue                                             */
@@ -88,6 +95,16 @@ typedef struct mi_problem {
   int32_t validate;      /* nonzero: check X is 0/1 first (one extra pass, blocking) */
   int32_t tile;          /* mi_tile; 0 = autotuned / heuristic                      */
   int32_t splits;        /* K-splits over the rows; 0 = autotuned / heuristic       */
+  /* Sparse output (blockwise use when the n x n matrix is not wanted or does
+   * not fit): every pair i < j with MI >= pairs_threshold is appended to
+   * `pairs`, in no particular order.  *pairs_count (device, zeroed by the
+   * call) receives the number of such pairs; if it exceeds pairs_capacity,
+   * only pairs_capacity of them (an unspecified subset) are stored.  The same
+   * evaluation as the dense output (same epilogue mode, same values). */
+  mi_pair* pairs;                   /* optional device array of pairs_capacity entries */
+  int64_t pairs_capacity;           /* >= 0                                           */
+  unsigned long long* pairs_count;  /* device; required when pairs is given           */
+  float pairs_threshold;            /* bits                                           */
 } mi_problem;
 
 /* Fill *p with defaults for X (m x n, ldx = n) and out: FP32 epilogue, auto config. */
@@ -104,8 +121,9 @@ mi_status mi_all_pairs_async(const uint8_t* X, int64_t m, int64_t n, float* out,
 mi_status mi_all_pairs_ex(const mi_problem* p, void* stream);
 
 /* Many independent datasets in one call, asynchronous on `stream`.
- *   mode MI_BATCH_PERSISTENT: one persistent launch per tile configuration
- *        pulls (dataset, tile, split) work units from a device queue;
+ *   mode MI_BATCH_PERSISTENT: one persistent launch (per tile configuration
+ *        when tiles are forced) pulls (dataset, tile, split) work units from
+ *        a device queue, after one launch that repacks every unaligned input;
  *   mode MI_BATCH_GRAPH: `count` plain launches captured once into a hipGraph
  *        and replayed (the graph is cached for identical batches);
  *   mode MI_BATCH_SEQUENTIAL: `count` plain launches, one after another.
@@ -121,9 +139,10 @@ mi_status mi_all_pairs_batched(const mi_problem* probs, int64_t count, void* str
 mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits);
 
 /* Autotuner: time the candidate (tile, splits) configurations for this shape
- * on the current device (on a scratch zero matrix: the kernel's time does not
- * depend on the data) and remember the fastest for every later call with the
- * same shape class.  *best_ms receives its time (may be NULL). */
+ * on the current device (on a scratch all-ones matrix: every split-K partial
+ * is then published, the costly case) and remember the fastest for every
+ * later call with the same shape class.  *best_ms receives its time (may be
+ * NULL). */
 mi_status mi_tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms);
 mi_status mi_tuner_save(const char* path);   /* JSON lines */
 mi_status mi_tuner_load(const char* path);

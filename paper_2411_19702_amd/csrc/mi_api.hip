@@ -271,7 +271,12 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   const int64_t ldx = p->ldx == 0 ? p->n : p->ldx;
   if (ldx < p->n) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)p->n);
   if (ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) above the supported 2^24", (long long)ldx);
-  if (p->n > 0 && (!p->X || !p->out)) return fail(MI_ERR_INVALID_ARG, "X and out must be non-NULL when n > 0");
+  if (p->n > 0 && !p->X) return fail(MI_ERR_INVALID_ARG, "X must be non-NULL when n > 0");
+  if (p->n > 0 && !p->out && !p->pairs)
+    return fail(MI_ERR_INVALID_ARG, "out (or the sparse pairs output) must be given when n > 0");
+  if (p->pairs && (!p->pairs_count || p->pairs_capacity < 0 || !std::isfinite(p->pairs_threshold)))
+    return fail(MI_ERR_INVALID_ARG, "pairs needs pairs_count, pairs_capacity >= 0 and a finite threshold");
+
   if (p->epilogue < 0 || p->epilogue > 2) return fail(MI_ERR_INVALID_ARG, "bad epilogue mode %d", p->epilogue);
   if (p->tile < 0 || p->tile > 2) return fail(MI_ERR_INVALID_ARG, "bad tile id %d", p->tile);
   if (p->splits < 0) return fail(MI_ERR_INVALID_ARG, "splits must be >= 0");
@@ -290,6 +295,10 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
   P.m = (int32_t)p->m;
   P.n = (int32_t)p->n;
   P.out = p->out;
+  P.pairs = reinterpret_cast<int32_t*>(p->pairs);
+  P.pairs_cap = p->pairs_capacity;
+  P.pairs_count = p->pairs_count;
+  P.thr = p->pairs_threshold;
   P.n11_out = p->n11_out;
   P.colsum_out = p->colsum_out;
   P.tiles = tiles;
@@ -335,6 +344,7 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot) {
   int64_t ldx = 0;
   mi_status s = check_problem(p, &ldx);
   if (s != MI_OK) return s;
+  if (p->pairs) HIPCHK(fill_i32(reinterpret_cast<int*>(p->pairs_count), 0, 2, st));  // 64-bit counter
   if (p->n == 0) return MI_OK;
   if (p->validate) {
     s = validate_binary(p, ldx, st);
@@ -391,9 +401,10 @@ static std::string batch_key(const mi_problem* probs, int64_t count, const std::
   k += buf;
   for (int64_t d = 0; d < count; ++d) {
     const mi_problem& p = probs[d];
-    snprintf(buf, sizeof buf, "%p,%lld,%lld,%lld,%p,%p,%p,%d,%g,%d,%d;", (const void*)p.X, (long long)p.m,
-             (long long)p.n, (long long)p.ldx, (void*)p.out, (void*)p.n11_out, (void*)p.colsum_out, p.epilogue,
-             (double)p.fallback_tau, plans[d].cfg, plans[d].splits);
+    snprintf(buf, sizeof buf, "%p,%lld,%lld,%lld,%p,%p,%p,%d,%g,%d,%d,%p,%lld,%p,%a;", (const void*)p.X,
+             (long long)p.m, (long long)p.n, (long long)p.ldx, (void*)p.out, (void*)p.n11_out, (void*)p.colsum_out,
+             p.epilogue, (double)p.fallback_tau, plans[d].cfg, plans[d].splits, (void*)p.pairs,
+             (long long)p.pairs_capacity, (void*)p.pairs_count, (double)p.pairs_threshold);
     k += buf;
   }
   return k;
@@ -508,8 +519,10 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
 
   if (mode == MI_BATCH_SEQUENTIAL) {
     HIPCHK(repack_all());
-    for (int64_t d = 0; d < count; ++d)
+    for (int64_t d = 0; d < count; ++d) {
+      if (probs[d].pairs) HIPCHK(fill_i32(reinterpret_cast<int*>(probs[d].pairs_count), 0, 2, st));
       if (probs[d].n > 0) HIPCHK(launch_plain(plans[d].cfg, P[d], st));
+    }
     return MI_OK;
   }
 
@@ -540,7 +553,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
       HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipSuccess;
       for (int64_t d = 0; d < count && e == hipSuccess; ++d) {
-        if (probs[d].n == 0) continue;
+        if (probs[d].pairs) e = fill_i32(reinterpret_cast<int*>(probs[d].pairs_count), 0, 2, cap);
+        if (e != hipSuccess || probs[d].n == 0) continue;
         if (!aligned[d])
           e = launch_repack(probs[d].X, probs[d].m, probs[d].n, ldx[d], (uint8_t*)P[d].X, P[d].ldx, cap);
         if (e == hipSuccess) e = launch_plain(plans[d].cfg, P[d], cap);
@@ -634,6 +648,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   if (!rdesc.empty()) std::memcpy(h + probs_bytes + units_bytes, rdesc.data(), sizeof(RepackDesc) * rdesc.size());
   HIPCHK(hipMemcpyAsync(bb.dev, bb.host, probs_bytes + units_bytes + rdesc_bytes, hipMemcpyHostToDevice, st));
   HIPCHK(hipEventRecord(bb.copied, st));
+  for (int64_t d = 0; d < count; ++d)
+    if (probs[d].pairs) HIPCHK(fill_i32(reinterpret_cast<int*>(probs[d].pairs_count), 0, 2, st));
   char* dv = (char*)bb.dev;
   HIPCHK(launch_repack_batch((const RepackDesc*)(dv + probs_bytes + units_bytes), (int)rdesc.size(), rblocks, st));
   const ProbDev* dP = (const ProbDev*)dv;

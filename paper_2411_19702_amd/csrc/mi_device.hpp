@@ -87,6 +87,12 @@ struct ProbDev {
   int32_t tiles_per_xcd;  // plain launch: tiles owned by each of the 8 XCDs
   int32_t epi;          // mi_epilogue
   float tau;
+  // Sparse output: pairs i < j with MI >= thr, appended at an atomic counter
+  // (stored while the count stays below cap).  pairs == nullptr: none.
+  int32_t* pairs;       // cap entries of (i, j, MI as FP32 bits)
+  int64_t pairs_cap;
+  unsigned long long* pairs_count;
+  float thr;
 };
 
 // ---------------------------------------------------------------------------
@@ -542,8 +548,28 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       }
       sM[e] = v;
       if (i < n && j < n && (!diag || j >= i)) {
-        P.out[i * ln + j] = v;
+        if (P.out) P.out[i * ln + j] = v;
         if (P.n11_out) P.n11_out[i * ln + j] = v11;
+      }
+      if (P.pairs) {
+        // Sparse output: one atomic per wave and row, lanes in order.
+        const bool q = i < n && j < n && j > i && v >= P.thr;
+        const unsigned long long mask = __ballot(q);
+        if (mask) {  // uniform
+          const int leader = __ffsll((long long)mask) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(P.pairs_count, (unsigned long long)__popcll(mask));
+          base = __shfl(base, leader);
+          if (q) {
+            const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+            if (idx < (unsigned long long)P.pairs_cap) {
+              int32_t* e3 = P.pairs + 3 * idx;
+              e3[0] = i;
+              e3[1] = j;
+              e3[2] = __float_as_int(v);
+            }
+          }
+        }
       }
     }
   };
@@ -571,11 +597,11 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     }
     __builtin_amdgcn_wave_barrier();
     // Mirror rows (consecutive lanes, consecutive i).
-    for (int e = lane; e < STRIP; e += 64) {
+    for (int e = lane; e < STRIP && (P.out || P.n11_out); e += 64) {
       const int cc = e / 32, rr = e % 32;
       const int i = i0 + rr, jm = jbase + cc;
       if (i < n && jm < n && (!diag || jm > i)) {
-        P.out[jm * ln + i] = sM[rr * WTN + cc];
+        if (P.out) P.out[jm * ln + i] = sM[rr * WTN + cc];
         if (P.n11_out) P.n11_out[jm * ln + i] = sN[rr * WTN + cc];
       }
     }

@@ -102,7 +102,9 @@ namespace {
 
 // Device memory a request holds while it is admitted.
 size_t request_bytes(const mi_problem& p, int64_t ldx) {
-  size_t b = (size_t)p.m * (size_t)ldx + (size_t)p.n * (size_t)p.n * sizeof(float);
+  size_t b = (size_t)p.m * (size_t)ldx;
+  if (p.out) b += (size_t)p.n * (size_t)p.n * sizeof(float);
+  if (p.pairs) b += (size_t)p.pairs_capacity * sizeof(mi_pair) + sizeof(unsigned long long);
   if (p.n11_out) b += (size_t)p.n * (size_t)p.n * sizeof(int32_t);
   if (p.colsum_out) b += (size_t)p.n * sizeof(int32_t);
   if (p.n > 0) {

@@ -51,6 +51,10 @@ class mi_problem(ctypes.Structure):
         ("validate", ctypes.c_int32),
         ("tile", ctypes.c_int32),
         ("splits", ctypes.c_int32),
+        ("pairs", ctypes.c_void_p),
+        ("pairs_capacity", ctypes.c_int64),
+        ("pairs_count", ctypes.c_void_p),
+        ("pairs_threshold", ctypes.c_float),
     ]
 
 
@@ -136,23 +140,45 @@ def _x_layout(X: torch.Tensor, n: Optional[int]) -> Tuple[int, int, int]:
     return m, n, ldx
 
 
-def make_problem(X: torch.Tensor, out: torch.Tensor, n: Optional[int] = None, n11_out: Optional[torch.Tensor] = None,
-                 colsum_out: Optional[torch.Tensor] = None, epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3,
-                 validate: bool = False, tile: int = 0, splits: int = 0) -> mi_problem:
+def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] = None,
+                 n11_out: Optional[torch.Tensor] = None, colsum_out: Optional[torch.Tensor] = None,
+                 epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3, validate: bool = False, tile: int = 0,
+                 splits: int = 0, pairs: Optional[torch.Tensor] = None, pairs_count: Optional[torch.Tensor] = None,
+                 pairs_threshold: float = 0.0) -> mi_problem:
+    """pairs: int32 GPU tensor of shape (capacity, 3) receiving (i, j, MI bits as FP32) rows;
+    pairs_count: int64 GPU tensor with one element (the number of qualifying pairs)."""
     m, n, ldx = _x_layout(X, n)
-    for name, t, dt in (("out", out, torch.float32), ("n11_out", n11_out, torch.int32), ("colsum_out", colsum_out, torch.int32)):
+    for name, t, dt in (("out", out, torch.float32), ("n11_out", n11_out, torch.int32),
+                        ("colsum_out", colsum_out, torch.int32), ("pairs", pairs, torch.int32),
+                        ("pairs_count", pairs_count, torch.int64)):
         if t is None:
             continue
         if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
             raise ValueError(f"{name} must be a contiguous {dt} GPU tensor")
-    if out.numel() < n * n or (n11_out is not None and n11_out.numel() < n * n) or (colsum_out is not None and colsum_out.numel() < n):
+    if (out is not None and out.numel() < n * n) or (n11_out is not None and n11_out.numel() < n * n) or \
+            (colsum_out is not None and colsum_out.numel() < n):
         raise ValueError("output tensor too small")
+    if pairs is not None and (pairs.dim() != 2 or pairs.shape[1] != 3 or pairs_count is None or pairs_count.numel() < 1):
+        raise ValueError("pairs must be (capacity, 3) int32 with a one-element int64 pairs_count")
     p = mi_problem()
     p.X, p.m, p.n, p.ldx = X.data_ptr(), m, n, ldx
-    p.out, p.n11_out, p.colsum_out = out.data_ptr(), _ptr(n11_out), _ptr(colsum_out)
+    p.out, p.n11_out, p.colsum_out = _ptr(out), _ptr(n11_out), _ptr(colsum_out)
     p.epilogue, p.fallback_tau, p.validate = int(epilogue), float(fallback_tau), 1 if validate else 0
     p.tile, p.splits = int(tile), int(splits)
+    p.pairs, p.pairs_capacity = _ptr(pairs), (pairs.shape[0] if pairs is not None else 0)
+    p.pairs_count, p.pairs_threshold = _ptr(pairs_count), float(pairs_threshold)
     return p
+
+
+def mi_all_pairs_threshold(X: torch.Tensor, threshold: float, capacity: int, dense_out: Optional[torch.Tensor] = None,
+                           stream=None, **kw):
+    """Sparse output: (pairs, count) where pairs[:min(count, capacity)] holds the (i, j, MI) rows
+    with i < j and MI >= threshold (order unspecified); count (GPU int64 tensor) is the total."""
+    pairs = torch.empty((max(int(capacity), 0), 3), dtype=torch.int32, device=X.device)
+    count = torch.empty((1,), dtype=torch.int64, device=X.device)
+    p = make_problem(X, dense_out, pairs=pairs, pairs_count=count, pairs_threshold=threshold, **kw)
+    _check(lib().mi_all_pairs_ex(ctypes.byref(p), _stream_handle(stream)))
+    return pairs, count
 
 
 def _new_out(X: torch.Tensor, n: Optional[int]) -> torch.Tensor:

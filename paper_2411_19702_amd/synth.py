@@ -241,6 +241,16 @@ def spec_outbound(seed: int = SEED0 + 5, m: int = 2000, n: int = 8192) -> Datase
     return DatasetSpec(m=m, n=n, seed=seed, p=p, planted=planted, name=f"outbound_{m}x{n}")
 
 
+def spec_wide(seed: int = SEED0 + 6, m: int = 20_000, n: int = 32_768) -> DatasetSpec:
+    """20,000 x 32,768 (many variables: the dense FP32 output would be 4.3 GB,
+    the use case of the sparse threshold output); p_j log-uniform in
+    [0.01, 0.3]; floor(0.5% n) planted pairs, q ~ U[0, 0.3]."""
+    rng = np.random.default_rng(seed)
+    p = np.exp(rng.uniform(math.log(0.01), math.log(0.3), size=n))
+    planted = _pick_planted(rng, n, n // 200, 0.3, set())
+    return DatasetSpec(m=m, n=n, seed=seed, p=p, planted=planted, name=f"wide_{m}x{n}")
+
+
 def _log_uniform_int(rng: np.random.Generator, lo: int, hi: int) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
 

@@ -140,3 +140,22 @@ def test_server_argument_checks_on_host(L):
     assert L.mi_server_poll(None, 1) == 1
     assert L.mi_server_wait(None, 1, 0.0, None) == 1
     assert L.mi_server_destroy(None) == 1
+
+
+def test_sparse_output_argument_checks(L):
+    """Sparse (threshold) output: pairs need a counter, capacity >= 0 and a finite
+    threshold; out may be NULL only when pairs is given."""
+    import math
+    from paper_2411_19702_amd import mi
+    P = mi.mi_problem
+    def prob(**kw):
+        p = P()
+        p.X, p.m, p.n, p.ldx, p.out = 16, 10, 8, 8, 0
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+    assert L.mi_all_pairs_ex(ctypes.byref(prob()), None) == 1                      # neither out nor pairs
+    assert L.mi_all_pairs_ex(ctypes.byref(prob(pairs=64, pairs_capacity=4)), None) == 1   # no counter
+    assert L.mi_all_pairs_ex(ctypes.byref(prob(pairs=64, pairs_capacity=-1, pairs_count=128)), None) == 1
+    assert L.mi_all_pairs_ex(ctypes.byref(prob(pairs=64, pairs_capacity=4, pairs_count=128,
+                                                pairs_threshold=math.nan)), None) == 1
