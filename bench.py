@@ -200,6 +200,32 @@ def bench_sparse(dev, thr: float = 0.01, reps: int = 3):
             "sparse_output_bytes": 12 * min(found, cap)}
 
 
+def bench_sparse_input(dev, densities=(0.001, 0.005, 0.02), reps: int = 3):
+    """The sparse-input path against the dense int8 path on 1,000,000 x 4,096
+    matrices of mean density d (p_j ~ U[0, 2d]): blocking call time each."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    res = []
+    for d in densities:
+        spec = synth.spec_random(11, 1_000_000, 4096, 0.0, 2.0 * d)
+        X = synth.generate(spec, device=dev)
+        out = torch.empty((4096, 4096), dtype=torch.float32, device=dev)
+        row = {"density": d}
+        for name, algo in (("dense", mi.MI_ALGO_DENSE), ("sparse", mi.MI_ALGO_SPARSE), ("auto", mi.MI_ALGO_AUTO)):
+            mi.mi_all_pairs_ex(X, out=out, algo=algo)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                mi.mi_all_pairs_ex(X, out=out, algo=algo)
+                torch.cuda.synchronize()
+            row[name + "_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        res.append(row)
+        print(f"[sparse-input] {row}", file=sys.stderr, flush=True)
+        del X, out
+        torch.cuda.empty_cache()
+    return {"workload": "1000000x4096, p_j ~ U[0, 2d]", "rows": res}
+
+
 def bench_batched(dev, reps: int = 3):
     """256 independent datasets: one persistent launch vs a replayed hipGraph
     of plain launches vs 256 sequential plain calls (same results, bitwise)."""
@@ -321,7 +347,7 @@ def main() -> int:
     ap.add_argument("--tile", type=int, default=0, help="force a tile config (1: 128, 2: 256)")
     ap.add_argument("--splits", type=int, default=0, help="force the K-split count")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra measurements")
-    ap.add_argument("--extras", default="configs,batched,served,sparse",
+    ap.add_argument("--extras", default="configs,batched,served,sparse,sparse_input",
                     help="comma list of extra measurements: configs (the 1000 x 200 and 100000 x 1024 "
                          "workloads), batched (256 datasets), served (Poisson request trace), sparse (threshold "
                          "output on 20000 x 32768)")
@@ -429,6 +455,8 @@ def main() -> int:
         rec["served"] = bench_served(dev, slots=args.served_slots)
     if "sparse" in extras:
         rec["sparse"] = bench_sparse(dev)
+    if "sparse_input" in extras:
+        rec["sparse_input"] = bench_sparse_input(dev)
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

@@ -75,6 +75,16 @@ typedef enum mi_tile {
   MI_TILE_256 = 2   /* 256 x 256 output tile, 8 waves of 128 x 64 */
 } mi_tile;
 
+/* How the 1-1 counts are computed. */
+typedef enum mi_algo {
+  MI_ALGO_DENSE = 0,   /* int8 matrix-core Gram over upper-triangular tiles (default)        */
+  MI_ALGO_SPARSE = 1,  /* sum over rows of the pairs of ones (work ~ m (n d)^2 at density d);  */
+                       /* synchronises the stream once                                        */
+  MI_ALGO_AUTO = 2     /* count the ones and their pairs first (one pass, synchronises) and */
+                       /* take whichever path a cost model from measured rates says is     */
+                       /* faster (at 1M x 4096 the sparse one below ~0.3% density)          */
+} mi_algo;
+
 /* One entry of the sparse (threshold) output: MI(X_i; X_j) in bits, i < j. */
 typedef struct mi_pair {
   int32_t i, j;
@@ -105,6 +115,7 @@ typedef struct mi_problem {
   int64_t pairs_capacity;           /* >= 0                                           */
   unsigned long long* pairs_count;  /* device; required when pairs is given           */
   float pairs_threshold;            /* bits                                           */
+  int32_t algo;                     /* mi_algo; batches and the server take only DENSE */
 } mi_problem;
 
 /* Fill *p with defaults for X (m x n, ldx = n) and out: FP32 epilogue, auto config. */

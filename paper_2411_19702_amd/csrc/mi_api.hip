@@ -274,6 +274,7 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   if (p->n > 0 && !p->X) return fail(MI_ERR_INVALID_ARG, "X must be non-NULL when n > 0");
   if (p->n > 0 && !p->out && !p->pairs)
     return fail(MI_ERR_INVALID_ARG, "out (or the sparse pairs output) must be given when n > 0");
+  if (p->algo < MI_ALGO_DENSE || p->algo > MI_ALGO_AUTO) return fail(MI_ERR_INVALID_ARG, "bad algo %d", p->algo);
   if (p->pairs && (!p->pairs_count || p->pairs_capacity < 0 || !std::isfinite(p->pairs_threshold)))
     return fail(MI_ERR_INVALID_ARG, "pairs needs pairs_count, pairs_capacity >= 0 and a finite threshold");
 
@@ -349,6 +350,11 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot) {
   if (p->validate) {
     s = validate_binary(p, ldx, st);
     if (s != MI_OK) return s;
+  }
+  if (p->algo != MI_ALGO_DENSE) {
+    bool used = false;
+    s = run_sparse(p, ldx, st, p->algo == MI_ALGO_AUTO, &used);
+    if (s != MI_OK || used) return s;
   }
   const bool aligned = is_aligned(p->X, ldx);
   Plan pl;
@@ -426,6 +432,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
       return fail(s, "problem %lld: %s", (long long)d, why.c_str());
     }
     if (probs[d].validate) return fail(MI_ERR_INVALID_ARG, "problem %lld: validate is not supported in batches", (long long)d);
+    if (probs[d].algo != MI_ALGO_DENSE)
+      return fail(MI_ERR_INVALID_ARG, "problem %lld: batches take only the dense algorithm", (long long)d);
   }
   DeviceInfo di;
   s = device_info(&di);

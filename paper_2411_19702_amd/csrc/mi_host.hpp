@@ -50,6 +50,9 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
 mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out);
 int64_t packed_pitch(int64_t n);
 mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot);
+// Sparse-input path (mi_sparse.hip).  With auto_choice it first measures the
+// density and returns with *used == false when the dense path is cheaper.
+mi_status run_sparse(const mi_problem* p, int64_t ldx, hipStream_t st, bool auto_choice, bool* used);
 void release_scratch_of(hipStream_t st);
 void release_stream_resources(hipStream_t st);  // scratch and batch descriptors of a stream
 mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode);

@@ -26,6 +26,7 @@ STATUS_NAMES = {
     5: "MI_ERR_QUEUE_FULL", 6: "MI_ERR_NOT_READY", 7: "MI_ERR_DEVICE", 8: "MI_ERR_TIMEOUT", 9: "MI_ERR_UNKNOWN_TICKET",
 }
 MI_EPI_FP32, MI_EPI_FP32_FP64_FALLBACK, MI_EPI_FP64 = 0, 1, 2
+MI_ALGO_DENSE, MI_ALGO_SPARSE, MI_ALGO_AUTO = 0, 1, 2
 MI_TILE_AUTO, MI_TILE_128, MI_TILE_256 = 0, 1, 2
 MI_BATCH_PERSISTENT, MI_BATCH_GRAPH, MI_BATCH_SEQUENTIAL = 0, 1, 2
 
@@ -55,6 +56,7 @@ class mi_problem(ctypes.Structure):
         ("pairs_capacity", ctypes.c_int64),
         ("pairs_count", ctypes.c_void_p),
         ("pairs_threshold", ctypes.c_float),
+        ("algo", ctypes.c_int32),
     ]
 
 
@@ -144,7 +146,7 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
                  n11_out: Optional[torch.Tensor] = None, colsum_out: Optional[torch.Tensor] = None,
                  epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3, validate: bool = False, tile: int = 0,
                  splits: int = 0, pairs: Optional[torch.Tensor] = None, pairs_count: Optional[torch.Tensor] = None,
-                 pairs_threshold: float = 0.0) -> mi_problem:
+                 pairs_threshold: float = 0.0, algo: int = 0) -> mi_problem:
     """pairs: int32 GPU tensor of shape (capacity, 3) receiving (i, j, MI bits as FP32) rows;
     pairs_count: int64 GPU tensor with one element (the number of qualifying pairs)."""
     m, n, ldx = _x_layout(X, n)
@@ -167,6 +169,7 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
     p.tile, p.splits = int(tile), int(splits)
     p.pairs, p.pairs_capacity = _ptr(pairs), (pairs.shape[0] if pairs is not None else 0)
     p.pairs_count, p.pairs_threshold = _ptr(pairs_count), float(pairs_threshold)
+    p.algo = int(algo)
     return p
 
 
