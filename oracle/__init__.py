@@ -6,7 +6,9 @@ imports the GPU library.
 
 `mi_oracle.c` holds the arithmetic: a per-pair loop over the rows that counts
 the four cells (n11, n10, n01, n00) in int64 and evaluates Eq. 1/Eq. 2 of the
-paper in FP64 with 0 log 0 = 0.  This module builds it with gcc and wraps it
+paper in FP64 with 0 log 0 = 0; for categorical variables (codes 0 .. L-1) the
+same loop counts an L_i x L_j contingency table and Eq. 1 runs over all of
+its cells.  This module builds it with gcc and wraps it
 with ctypes; the wrappers do argument marshalling only.
 """
 from __future__ import annotations
@@ -49,6 +51,13 @@ def _load():
         lib.mi_oracle_colsums.restype = ctypes.c_int
         lib.mi_oracle_from_counts.argtypes = [i64, i64, i64, i64]
         lib.mi_oracle_from_counts.restype = ctypes.c_double
+        i32 = ctypes.c_int32
+        lib.mi_oracle_cat_table.argtypes = [p, i64, i64, i64, i64, i32, i32, p]
+        lib.mi_oracle_cat_table.restype = ctypes.c_int
+        lib.mi_oracle_cat_from_table.argtypes = [p, i32, i32]
+        lib.mi_oracle_cat_from_table.restype = ctypes.c_double
+        lib.mi_oracle_cat_all.argtypes = [p, i64, i64, i64, p, p]
+        lib.mi_oracle_cat_all.restype = ctypes.c_int
         lib.mi_oracle_threads.argtypes = []
         lib.mi_oracle_threads.restype = ctypes.c_int
         _lib = lib
@@ -118,3 +127,45 @@ def colsums(X, n: Optional[int] = None) -> np.ndarray:
 def from_counts(n11: int, n10: int, n01: int, n00: int) -> float:
     """MI in bits of one pair from its four cell counts (Eq. 2)."""
     return float(_load().mi_oracle_from_counts(int(n11), int(n10), int(n01), int(n00)))
+
+
+def _levels(levels, v: int) -> np.ndarray:
+    lv = np.ascontiguousarray(levels, dtype=np.int32)
+    if lv.shape != (v,):
+        raise ValueError("levels must hold one count per variable")
+    return lv
+
+
+def cat_table(X, levels, i: int, j: int) -> np.ndarray:
+    """Contingency table (int64[L_i, L_j]) of categorical variables i and j."""
+    X = _as_u8(X)
+    m, ld = X.shape
+    lv = np.asarray(levels, dtype=np.int64)
+    Li, Lj = int(lv[i]), int(lv[j])
+    t = np.empty((Li, Lj), dtype=np.int64)
+    rc = _load().mi_oracle_cat_table(_ptr(X), m, ld, int(i), int(j), Li, Lj, _ptr(t))
+    if rc != 0:
+        raise ValueError(f"mi_oracle_cat_table rc={rc}")
+    return t
+
+
+def cat_from_table(table) -> float:
+    """MI in bits of one pair from its contingency table (Eq. 1 over all cells)."""
+    t = np.ascontiguousarray(table, dtype=np.int64)
+    if t.ndim != 2:
+        raise ValueError("table must be 2-D")
+    return float(_load().mi_oracle_cat_from_table(_ptr(t), t.shape[0], t.shape[1]))
+
+
+def cat_all_pairs(X, levels, v: Optional[int] = None) -> np.ndarray:
+    """MI float64[v, v] in bits between the first v categorical columns of X,
+    column j holding codes 0 .. levels[j] - 1."""
+    X = _as_u8(X)
+    m, ld = X.shape
+    v = ld if v is None else v
+    lv = _levels(levels, v)
+    mi = np.empty((v, v), dtype=np.float64)
+    rc = _load().mi_oracle_cat_all(_ptr(X), m, v, ld, _ptr(lv), _ptr(mi))
+    if rc != 0:
+        raise ValueError(f"mi_oracle_cat_all rc={rc}")
+    return mi

@@ -1,5 +1,6 @@
 /*
- * mi_oracle.c -- plain CPU oracle for all-pairs binary mutual information.
+ * mi_oracle.c -- plain CPU oracle for all-pairs binary mutual information,
+ * and for its extension to categorical variables (at the end of the file).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
  * reference that the GPU path is checked against.  It shares no code with the
@@ -28,6 +29,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 /* One cell's contribution, in bits, multiplied by m: n_xy * log2(n_xy m / (n_x n_y)). */
 static double cell_term(int64_t nxy, int64_t nx, int64_t ny, int64_t m)
@@ -134,4 +136,87 @@ int mi_oracle_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------
+ * Categorical variables (the extension to non-binary data named as future
+ * work in the Conclusions).  Eq. 1 is a sum over the joint value set of two
+ * discrete variables; the binary case restricts it to {0,1} x {0,1}.  Here
+ * variable j takes the codes 0 .. L_j - 1, the joint counts of a pair form an
+ * L_i x L_j contingency table, and
+ *
+ *   MI(X_i; X_j) = (1/m) sum_{x,y} n_xy log2( n_xy m / (r_x s_y) )
+ *
+ * with r_x and s_y the row and column sums of the table (the marginal
+ * counts) and 0 log 0 = 0 as above.  The table is counted by a direct loop
+ * over the rows, and the marginals are the table's own sums.
+ * ---------------------------------------------------------------------- */
+
+/* Contingency table of variables i and j: table[x * Lj + y] = number of rows
+ * with X_i = x and X_j = y.  Returns 2 if a code is not below its level count. */
+int mi_oracle_cat_table(const uint8_t* X, int64_t m, int64_t ldx, int64_t i, int64_t j,
+                        int32_t Li, int32_t Lj, int64_t* table)
+{
+    if (!X || !table || m <= 0 || Li < 1 || Lj < 1) return 1;
+    for (int64_t c = 0; c < (int64_t)Li * Lj; ++c) table[c] = 0;
+    for (int64_t k = 0; k < m; ++k) {
+        int x = X[k * ldx + i], y = X[k * ldx + j];
+        if (x >= Li || y >= Lj) return 2;
+        table[(int64_t)x * Lj + y] += 1;
+    }
+    return 0;
+}
+
+/* MI in bits of one pair from its contingency table. */
+double mi_oracle_cat_from_table(const int64_t* table, int32_t Li, int32_t Lj)
+{
+    int64_t m = 0, col[256];
+    if (Li < 1 || Lj < 1 || Lj > 256) return NAN;
+    for (int32_t y = 0; y < Lj; ++y) col[y] = 0;
+    for (int32_t x = 0; x < Li; ++x)
+        for (int32_t y = 0; y < Lj; ++y) {
+            col[y] += table[(int64_t)x * Lj + y];
+            m += table[(int64_t)x * Lj + y];
+        }
+    if (m <= 0) return NAN;
+    double s = 0.0;
+    for (int32_t x = 0; x < Li; ++x) {
+        int64_t r = 0;                                   /* row sum: marginal count of X_i = x */
+        for (int32_t y = 0; y < Lj; ++y) r += table[(int64_t)x * Lj + y];
+        for (int32_t y = 0; y < Lj; ++y) s += cell_term(table[(int64_t)x * Lj + y], r, col[y], m);
+    }
+    return s / (double)m;
+}
+
+/* The whole v x v matrix for variables with levels[j] codes each (1 <= levels[j]
+ * <= 256).  mi is v x v row-major, both triangles.  Returns 2 on a code out
+ * of range, 3 if a table cannot be allocated. */
+int mi_oracle_cat_all(const uint8_t* X, int64_t m, int64_t v, int64_t ldx, const int32_t* levels, double* mi)
+{
+    if (!X || !levels || !mi || m <= 0 || v < 0 || ldx < v) return 1;
+    for (int64_t j = 0; j < v; ++j)
+        if (levels[j] < 1 || levels[j] > 256) return 1;
+    int rc = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < v; ++i) {
+        int64_t* table = (int64_t*)malloc(sizeof(int64_t) * 256 * 256);
+        if (!table) {
+#pragma omp atomic write
+            rc = 3;
+            continue;
+        }
+        for (int64_t j = i; j < v; ++j) {
+            int r = mi_oracle_cat_table(X, m, ldx, i, j, levels[i], levels[j], table);
+            if (r != 0) {
+#pragma omp atomic write
+                rc = r;
+                break;
+            }
+            double val = mi_oracle_cat_from_table(table, levels[i], levels[j]);
+            mi[i * v + j] = val;
+            mi[j * v + i] = val;
+        }
+        free(table);
+    }
+    return rc;
 }
