@@ -58,7 +58,8 @@ typedef enum mi_status {
   MI_ERR_NOT_READY = 6,     /* server: ticket not finished yet (poll)         */
   MI_ERR_DEVICE = 7,        /* a HIP call failed                              */
   MI_ERR_TIMEOUT = 8,       /* server: wait timed out                         */
-  MI_ERR_UNKNOWN_TICKET = 9 /* server: ticket was never issued or already collected */
+  MI_ERR_UNKNOWN_TICKET = 9, /* server: ticket was never issued or already collected */
+  MI_ERR_BAD_CODE = 10       /* categorical, validate != 0: a code is not below its level count */
 } mi_status;
 
 /* How MI is evaluated from the exact counts (the counts are always exact). */
@@ -97,7 +98,8 @@ typedef struct mi_problem {
   int64_t n;             /* columns (variables), >= 0                               */
   int64_t ldx;           /* row pitch in bytes, >= n; 0 means n                     */
   float* out;            /* device, n x n FP32 row-major; may be NULL when `pairs`  */
-                         /* is given (then no dense matrix is written)              */
+                         /* or n11_out is given (then no dense MI matrix is written; */
+                         /* with neither out nor pairs no MI is evaluated at all)   */
   int32_t* n11_out;      /* optional device n x n int32: the 1-1 counts X^T X        */
   int32_t* colsum_out;   /* optional device int32[n]: column sums c                 */
   int32_t epilogue;      /* mi_epilogue                                             */
@@ -145,6 +147,56 @@ typedef enum mi_batch_mode {
   MI_BATCH_SEQUENTIAL = 2
 } mi_batch_mode;
 mi_status mi_all_pairs_batched(const mi_problem* probs, int64_t count, void* stream, int32_t mode);
+
+/* Categorical variables: the extension to non-binary data that the paper's
+ * Conclusions name as future work.  Column j of X holds codes
+ * 0 .. levels[j] - 1, and MI runs over the whole joint value set (Eq. 1):
+ *
+ *     MI_ab = (1/m) sum_{x,y} n_xy log2( n_xy m / (r_x s_y) )      [bits]
+ *
+ * with n_xy the L_a x L_b contingency table of the pair and r_x, s_y its
+ * marginal counts.  The matrix way, generalising Section 3.1: the codes
+ * 1 .. L_j - 1 of every variable become indicator columns (N = sum (L_j - 1)
+ * of them, in variable order); ONE int8 Gram product of the indicator matrix
+ * gives every cell with both codes >= 1, its column sums give the marginals
+ * of codes >= 1, and every cell with a code 0 follows from those and m, as
+ * n10, n01 and n00 follow from n11 (Eq. 6/7).  With every level count 2 the
+ * indicators are X itself and this is the binary computation.
+ *
+ * Steps, all on `stream`: expand X into the m x N indicator matrix (device
+ * scratch, about m * N bytes), the fused Gram kernel in a counts-only mode
+ * (upper triangle, N x N int32 scratch unless counts_out is given), then one
+ * thread per variable pair evaluates the table's MI (FP32 log2 per cell, or
+ * FP64 per `epilogue`) and writes both triangles of out.  Asynchronous unless
+ * validate is set; `levels` is read during the call only. */
+typedef struct mi_cat_problem {
+  const uint8_t* X;        /* device, m x ldx bytes, row-major codes                  */
+  int64_t m;               /* rows (samples), 1 .. 2^31 - 1                           */
+  int64_t v;               /* variables (columns), >= 0; v == 0 is a no-op            */
+  int64_t ldx;             /* row pitch in bytes, >= v; 0 means v                     */
+  const int32_t* levels;   /* HOST int32[v]: level count of each variable, 1 .. 256   */
+  float* out;              /* device v x v FP32 row-major, both triangles (bitwise    */
+                           /* symmetric); the diagonal holds H(X_j)                   */
+  int32_t epilogue;        /* mi_epilogue                                            */
+  float fallback_tau;      /* MI_EPI_FP32_FP64_FALLBACK threshold in bits; <= 0: 1e-3 */
+  int32_t validate;        /* nonzero: check every code is below its level count      */
+                           /* first (one extra pass, synchronises; MI_ERR_BAD_CODE).  */
+                           /* Without it an out-of-range code counts as code 0.       */
+  int32_t tile;            /* mi_tile of the Gram kernel; 0 = library's choice        */
+  int32_t splits;          /* K-splits of the Gram kernel; 0 = library's choice       */
+  int32_t* counts_out;     /* optional device N x N int32, both triangles: the        */
+                           /* indicator Gram (cells with both codes >= 1)             */
+  int32_t* sums_out;       /* optional device int32[N]: indicator column sums         */
+} mi_cat_problem;
+
+/* Fill *p with defaults (ldx = v, FP32 epilogue, library's configuration). */
+void mi_cat_problem_init(mi_cat_problem* p, const uint8_t* X, int64_t m, int64_t v, const int32_t* levels,
+                         float* out);
+
+/* Number of indicator columns N = sum (levels[j] - 1) (the side of counts_out). */
+mi_status mi_cat_indicators(const int32_t* levels, int64_t v, int64_t* N);
+
+mi_status mi_all_pairs_categorical(const mi_cat_problem* p, void* stream);
 
 /* Configuration the library would use for an (m, n, ldx) problem. */
 mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits);

@@ -272,8 +272,8 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   if (ldx < p->n) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)p->n);
   if (ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) above the supported 2^24", (long long)ldx);
   if (p->n > 0 && !p->X) return fail(MI_ERR_INVALID_ARG, "X must be non-NULL when n > 0");
-  if (p->n > 0 && !p->out && !p->pairs)
-    return fail(MI_ERR_INVALID_ARG, "out (or the sparse pairs output) must be given when n > 0");
+  if (p->n > 0 && !p->out && !p->pairs && !p->n11_out)
+    return fail(MI_ERR_INVALID_ARG, "out, n11_out or the sparse pairs output must be given when n > 0");
   if (p->algo < MI_ALGO_DENSE || p->algo > MI_ALGO_AUTO) return fail(MI_ERR_INVALID_ARG, "bad algo %d", p->algo);
   if (p->pairs && (!p->pairs_count || p->pairs_capacity < 0 || !std::isfinite(p->pairs_threshold)))
     return fail(MI_ERR_INVALID_ARG, "pairs needs pairs_count, pairs_capacity >= 0 and a finite threshold");
@@ -307,7 +307,7 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
   P.ntiles = pl.ntiles;
   P.ksteps = (int32_t)pl.ksteps;
   P.kchunk = pl.kchunk;
-  P.epi = p->epilogue;
+  P.epi = (!p->out && !p->pairs) ? kEpiCounts : p->epilogue;  // counts alone: no MI evaluated
   P.tau = p->fallback_tau > 0.0f ? p->fallback_tau : 1e-3f;
   P.splits = pl.splits;
   P.tiles_per_xcd = pl.tpx;
@@ -341,7 +341,7 @@ mi_status validate_binary(const mi_problem* p, int64_t ldx, hipStream_t st) {
   return MI_OK;
 }
 
-mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot) {
+mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_only) {
   int64_t ldx = 0;
   mi_status s = check_problem(p, &ldx);
   if (s != MI_OK) return s;
@@ -376,7 +376,8 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot) {
   hipError_t e;
   const int32_t* tiles = tile_table(pl.ntp, &e);
   if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(e));
-  const ProbDev P = make_probdev(p, X, ld, pl, ws, tiles);
+  ProbDev P = make_probdev(p, X, ld, pl, ws, tiles);
+  P.upper_only = upper_only ? 1 : 0;
   HIPCHK(launch_plain(pl.cfg, P, st));
   return MI_OK;
 }

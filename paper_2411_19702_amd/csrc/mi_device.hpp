@@ -67,6 +67,9 @@ struct Cfg {
 using Cfg128 = Cfg<128, 2, 2, 4>;  // 4 waves of 64 x 64; 65 KB LDS, 2 workgroups per CU
 using Cfg256 = Cfg<256, 2, 4, 4>;  // 8 waves of 128 x 64; 130 KB LDS, 1 workgroup per CU
 
+// Epilogue mode of a problem that asks for counts alone (no MI output).
+constexpr int kEpiCounts = 3;
+
 // Everything a unit needs to know about its dataset.
 struct ProbDev {
   const uint8_t* X;
@@ -85,7 +88,8 @@ struct ProbDev {
   int32_t splits;       // K splits per tile
   int32_t kchunk;       // rows per split, a multiple of KT
   int32_t tiles_per_xcd;  // plain launch: tiles owned by each of the 8 XCDs
-  int32_t epi;          // mi_epilogue
+  int32_t epi;          // mi_epilogue, or kEpiCounts: counts only, no MI evaluated
+  int32_t upper_only;   // nonzero: store i <= j only (no mirror writes)
   float tau;
   // Sparse output: pairs i < j with MI >= thr, appended at an atomic counter
   // (stored while the count stays below cap).  pairs == nullptr: none.
@@ -540,7 +544,9 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       const int v11 = sN[e];
       const int ci = sColA[il];
       float v;
-      if (epi == 2) {
+      if (epi == kEpiCounts) {
+        v = 0.0f;
+      } else if (epi == 2) {
         v = mi_value64(P.m, ci, cj, v11);
       } else {
         v = mi_value32(P.m, ci, cj, v11, rA1[il], rA0[il], r1j, r0j, rfm);
@@ -593,11 +599,12 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     switch (P.epi) {
       case 0: strip_rows(i0, std::integral_constant<int, 0>{}); break;
       case 1: strip_rows(i0, std::integral_constant<int, 1>{}); break;
-      default: strip_rows(i0, std::integral_constant<int, 2>{}); break;
+      case 2: strip_rows(i0, std::integral_constant<int, 2>{}); break;
+      default: strip_rows(i0, std::integral_constant<int, kEpiCounts>{}); break;
     }
     __builtin_amdgcn_wave_barrier();
     // Mirror rows (consecutive lanes, consecutive i).
-    for (int e = lane; e < STRIP && (P.out || P.n11_out); e += 64) {
+    for (int e = lane; e < STRIP && (P.out || P.n11_out) && !P.upper_only; e += 64) {
       const int cc = e / 32, rr = e % 32;
       const int i = i0 + rr, jm = jbase + cc;
       if (i < n && jm < n && (!diag || jm > i)) {

@@ -49,7 +49,8 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
                      const int32_t* tiles);
 mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out);
 int64_t packed_pitch(int64_t n);
-mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot);
+// upper_only: the fused kernel stores the i <= j half of n11_out and out only.
+mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_only = false);
 // Sparse-input path (mi_sparse.hip).  With auto_choice it first measures the
 // density and returns with *used == false when the dense path is cheaper.
 mi_status run_sparse(const mi_problem* p, int64_t ldx, hipStream_t st, bool auto_choice, bool* used);

@@ -24,6 +24,7 @@ MI_OK = 0
 STATUS_NAMES = {
     0: "MI_OK", 1: "MI_ERR_INVALID_ARG", 2: "MI_ERR_NOT_BINARY", 3: "MI_ERR_OUT_OF_MEMORY", 4: "MI_ERR_BUDGET",
     5: "MI_ERR_QUEUE_FULL", 6: "MI_ERR_NOT_READY", 7: "MI_ERR_DEVICE", 8: "MI_ERR_TIMEOUT", 9: "MI_ERR_UNKNOWN_TICKET",
+    10: "MI_ERR_BAD_CODE",
 }
 MI_EPI_FP32, MI_EPI_FP32_FP64_FALLBACK, MI_EPI_FP64 = 0, 1, 2
 MI_ALGO_DENSE, MI_ALGO_SPARSE, MI_ALGO_AUTO = 0, 1, 2
@@ -57,6 +58,24 @@ class mi_problem(ctypes.Structure):
         ("pairs_count", ctypes.c_void_p),
         ("pairs_threshold", ctypes.c_float),
         ("algo", ctypes.c_int32),
+    ]
+
+
+class mi_cat_problem(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("v", ctypes.c_int64),
+        ("ldx", ctypes.c_int64),
+        ("levels", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("epilogue", ctypes.c_int32),
+        ("fallback_tau", ctypes.c_float),
+        ("validate", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("splits", ctypes.c_int32),
+        ("counts_out", ctypes.c_void_p),
+        ("sums_out", ctypes.c_void_p),
     ]
 
 
@@ -100,6 +119,9 @@ def lib() -> ctypes.CDLL:
         "mi_server_get_stats": (i32, [vp, P(mi_server_stats)]),
         "mi_server_destroy": (i32, [vp]),
         "mi_version": (ctypes.c_char_p, []),
+        "mi_cat_problem_init": (None, [P(mi_cat_problem), vp, i64, i64, vp, vp]),
+        "mi_cat_indicators": (i32, [vp, i64, P(i64)]),
+        "mi_all_pairs_categorical": (i32, [P(mi_cat_problem), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -300,3 +322,60 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------------------- categorical --
+
+def _levels_array(levels, v: int):
+    lv = (ctypes.c_int32 * max(v, 1))()
+    vals = [int(x) for x in levels]
+    if len(vals) != v:
+        raise ValueError("levels must hold one count per variable")
+    for j, x in enumerate(vals):
+        lv[j] = x
+    return lv
+
+
+def mi_cat_indicators(levels) -> int:
+    """N = sum (levels[j] - 1): the side of the indicator count matrix."""
+    v = len(levels)
+    lv = _levels_array(levels, v)
+    N = ctypes.c_int64()
+    _check(lib().mi_cat_indicators(lv, v, ctypes.byref(N)))
+    return int(N.value)
+
+
+def mi_all_pairs_categorical(X: torch.Tensor, levels, out: Optional[torch.Tensor] = None, v: Optional[int] = None,
+                             epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3, validate: bool = False,
+                             tile: int = 0, splits: int = 0, counts_out: Optional[torch.Tensor] = None,
+                             sums_out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """MI matrix (v x v FP32, bits) of categorical X: column j holds codes 0 .. levels[j]-1.
+    X is a uint8 GPU tensor (m, cols) with contiguous rows; v defaults to cols."""
+    if not isinstance(X, torch.Tensor) or X.dim() != 2 or not X.is_cuda or X.dtype not in (torch.uint8, torch.int8):
+        raise ValueError("X must be a 2-D uint8 GPU tensor of codes")
+    m, cols = X.shape
+    if m > 1 and X.stride(1) != 1:
+        raise ValueError("X rows must be contiguous (stride(1) == 1)")
+    ldx = X.stride(0) if m > 1 else max(cols, 1)
+    v = cols if v is None else int(v)
+    if v > cols:
+        raise ValueError("v exceeds X.shape[1]")
+    lv = _levels_array(levels, v)
+    if out is None:
+        out = torch.empty((v, v), dtype=torch.float32, device=X.device)
+    for name, t, dt in (("out", out, torch.float32), ("counts_out", counts_out, torch.int32),
+                        ("sums_out", sums_out, torch.int32)):
+        if t is not None and (not t.is_cuda or t.dtype != dt or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt} GPU tensor")
+    N = sum(int(x) - 1 for x in levels[:v]) if v else 0
+    if out.numel() < v * v or (counts_out is not None and counts_out.numel() < N * N) or \
+            (sums_out is not None and sums_out.numel() < N):
+        raise ValueError("output tensor too small")
+    p = mi_cat_problem()
+    lib().mi_cat_problem_init(ctypes.byref(p), X.data_ptr(), m, v, ctypes.cast(lv, ctypes.c_void_p), out.data_ptr())
+    p.ldx = ldx
+    p.epilogue, p.fallback_tau, p.validate = int(epilogue), float(fallback_tau), 1 if validate else 0
+    p.tile, p.splits = int(tile), int(splits)
+    p.counts_out, p.sums_out = _ptr(counts_out), _ptr(sums_out)
+    _check(lib().mi_all_pairs_categorical(ctypes.byref(p), _stream_handle(stream)))
+    return out

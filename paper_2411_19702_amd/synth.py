@@ -296,3 +296,121 @@ def spec_random(seed: int, m: int, n: int, p_lo: float = 0.0, p_hi: float = 1.0,
     p = rng.uniform(p_lo, p_hi, size=n)
     pl = _pick_planted(rng, n, planted, 0.3, set()) if planted else []
     return DatasetSpec(m=m, n=n, seed=seed, p=p, planted=pl, ldx=ldx, name=f"rand_{m}x{n}")
+
+
+# ---------------------------------------------------------------------------
+# Categorical datasets (codes 0 .. L-1 per column).  Codes come from the same
+# counter-based hash: code = number of cumulative thresholds of the column
+# that u(seed, row, col) reaches, so P(code <= k) = cum[col, k].
+# ---------------------------------------------------------------------------
+
+_CODE, _CFLIP = 2, 3
+
+
+@dataclasses.dataclass
+class CatSpec:
+    """Everything needed to regenerate one m x v categorical matrix."""
+
+    m: int
+    v: int
+    seed: int
+    levels: np.ndarray                             # int32[v], codes per column (1 .. 256)
+    cum: np.ndarray                                # float64[v, Lmax - 1], P(code <= k); 1.0 past L - 2
+    planted: List[Tuple[int, int, float]] = dataclasses.field(default_factory=list)
+    # (dst, src, q): column dst := (code of src) mod L_dst, except where a Bernoulli(q) draw keeps its own code
+    ldx: Optional[int] = None
+    name: str = ""
+
+    @property
+    def pitch(self) -> int:
+        return self.v if self.ldx is None else self.ldx
+
+    def thresholds(self) -> np.ndarray:
+        return np.floor(np.clip(self.cum, 0.0, 1.0) * 4294967296.0).astype(np.int64)
+
+
+def _cat_base(spec: CatSpec, rows: torch.Tensor, cols: Sequence[int], device) -> torch.Tensor:
+    cols = list(cols)
+    cols_t = torch.as_tensor(cols, dtype=torch.int64, device=device)
+    thr = torch.as_tensor(spec.thresholds()[cols], dtype=torch.int64, device=device)   # (k, Lmax - 1)
+    u = uniform_u32(spec.seed, _CODE, rows, cols_t)
+    code = torch.zeros(u.shape, dtype=torch.int64, device=device)
+    for k in range(thr.shape[1]):
+        code += (u >= thr[None, :, k]).to(torch.int64)
+    return code.to(torch.uint8)
+
+
+def _cat_block(spec: CatSpec, rows: torch.Tensor, cols: Sequence[int], device) -> torch.Tensor:
+    cols = list(cols)
+    need = sorted(set(cols) | {src for dst, src, _q in spec.planted if dst in set(cols)})
+    index = {c: k for k, c in enumerate(need)}
+    block = _cat_base(spec, rows, need, device)
+    for dst, src, q in spec.planted:
+        if dst not in index:
+            continue
+        thr = int(math.floor(q * 4294967296.0))
+        u = uniform_u32(spec.seed, _CFLIP, rows, torch.tensor([dst], dtype=torch.int64, device=device))[:, 0]
+        keep = u < thr
+        copied = (block[:, index[src]].to(torch.int64) % int(spec.levels[dst])).to(torch.uint8)
+        block[:, index[dst]] = torch.where(keep, block[:, index[dst]], copied)
+    sel = torch.as_tensor([index[c] for c in cols], dtype=torch.int64, device=device)
+    return block.index_select(1, sel)
+
+
+def cat_columns(spec: CatSpec, cols: Sequence[int], device="cpu", row_chunk: int = 1 << 18) -> torch.Tensor:
+    """Regenerate only the listed columns: uint8 (m, len(cols)), C-contiguous."""
+    cols = list(cols)
+    out = torch.empty((spec.m, len(cols)), dtype=torch.uint8, device=device)
+    for r0 in range(0, spec.m, row_chunk):
+        r1 = min(spec.m, r0 + row_chunk)
+        rows = torch.arange(r0, r1, dtype=torch.int64, device=device)
+        out[r0:r1] = _cat_block(spec, rows, cols, device)
+    return out
+
+
+def cat_generate(spec: CatSpec, device="cpu", row_chunk: Optional[int] = None) -> torch.Tensor:
+    """The whole matrix as uint8 (m, pitch); bytes in columns >= v are zero."""
+    m, v, ld = spec.m, spec.v, spec.pitch
+    out = torch.zeros((m, ld), dtype=torch.uint8, device=device)
+    if v == 0:
+        return out
+    if row_chunk is None:
+        row_chunk = max(1, (1 << 25) // max(1, v * max(1, spec.cum.shape[1])))
+    for r0 in range(0, m, row_chunk):
+        r1 = min(m, r0 + row_chunk)
+        rows = torch.arange(r0, r1, dtype=torch.int64, device=out.device)
+        out[r0:r1, :v] = _cat_block(spec, rows, range(v), out.device)
+    return out
+
+
+def _cat_spec(seed: int, m: int, probs: List[np.ndarray], planted, ldx, name) -> CatSpec:
+    v = len(probs)
+    levels = np.array([len(p) for p in probs], dtype=np.int32)
+    width = max(1, int(levels.max(initial=1)) - 1)
+    cum = np.ones((v, width), dtype=np.float64)
+    for j, p in enumerate(probs):
+        c = np.cumsum(p)[:-1]
+        cum[j, :len(c)] = c
+    return CatSpec(m=m, v=v, seed=seed, levels=levels, cum=cum, planted=planted, ldx=ldx, name=name)
+
+
+def spec_genotypes(seed: int = SEED0 + 7, m: int = 1_000_000, v: int = 2048, ldx: Optional[int] = None) -> CatSpec:
+    """Genotype-like data: 3 codes per column with Hardy-Weinberg frequencies
+    (1-f)^2, 2f(1-f), f^2 for a minor-allele frequency f ~ U[0.05, 0.5], and
+    v // 100 planted pairs copying a column with probability 1 - q, q ~ U[0, 0.3]."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.05, 0.5, size=v)
+    probs = [np.array([(1 - a) ** 2, 2 * a * (1 - a), a * a]) for a in f]
+    planted = _pick_planted(rng, v, v // 100, 0.3, set())
+    return _cat_spec(seed, m, probs, planted, ldx, f"genotypes_{m}x{v}")
+
+
+def spec_categorical(seed: int, m: int, v: int, lmin: int = 2, lmax: int = 16, ldx: Optional[int] = None,
+                     planted: int = 0, alpha: float = 0.7, levels: Optional[Sequence[int]] = None) -> CatSpec:
+    """Generic categorical data for tests: level counts uniform in [lmin, lmax]
+    (or given), code probabilities Dirichlet(alpha), optional planted pairs."""
+    rng = np.random.default_rng(seed)
+    lv = rng.integers(lmin, lmax + 1, size=v) if levels is None else np.asarray(levels)
+    probs = [rng.dirichlet(np.full(int(L), alpha)) if L > 1 else np.array([1.0]) for L in lv]
+    pl = _pick_planted(rng, v, planted, 0.3, set()) if planted else []
+    return _cat_spec(seed, m, probs, pl, ldx, f"cat_{m}x{v}")

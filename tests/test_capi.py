@@ -159,3 +159,37 @@ def test_sparse_output_argument_checks(L):
     assert L.mi_all_pairs_ex(ctypes.byref(prob(pairs=64, pairs_capacity=-1, pairs_count=128)), None) == 1
     assert L.mi_all_pairs_ex(ctypes.byref(prob(pairs=64, pairs_capacity=4, pairs_count=128,
                                                 pairs_threshold=math.nan)), None) == 1
+
+
+def test_categorical_argument_checks(L):
+    """Categorical entry points: level counts 1 .. 256, non-NULL buffers, and the
+    indicator count N = sum (L_j - 1), all checked on the host."""
+    from paper_2411_19702_amd import mi
+    lv = (ctypes.c_int32 * 4)(3, 1, 256, 2)
+    N = ctypes.c_int64(-1)
+    assert L.mi_cat_indicators(lv, 4, ctypes.byref(N)) == 0 and N.value == 2 + 0 + 255 + 1
+    assert L.mi_cat_indicators(lv, 0, ctypes.byref(N)) == 0 and N.value == 0
+    assert L.mi_cat_indicators(None, 3, ctypes.byref(N)) == 1
+    bad = (ctypes.c_int32 * 2)(3, 0)
+    assert L.mi_cat_indicators(bad, 2, ctypes.byref(N)) == 1
+    big = (ctypes.c_int32 * 2)(257, 2)
+    assert L.mi_cat_indicators(big, 2, ctypes.byref(N)) == 1
+
+    def prob(lvs, **kw):
+        p = mi.mi_cat_problem()
+        L.mi_cat_problem_init(ctypes.byref(p), 16, 10, len(lvs), ctypes.cast(lvs, ctypes.c_void_p), 32)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+    assert L.mi_all_pairs_categorical(None, None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(bad)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(big)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, out=None)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, levels=None)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, m=0)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, ldx=3)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, epilogue=3)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, tile=5)), None) == 1
+    empty = mi.mi_cat_problem()
+    L.mi_cat_problem_init(ctypes.byref(empty), None, 5, 0, None, None)
+    assert L.mi_all_pairs_categorical(ctypes.byref(empty), None) == 0        # v == 0: no-op

@@ -1,0 +1,214 @@
+"""GPU: all-pairs MI of categorical variables against the categorical oracle.
+
+The indicator counts (the Gram product of the codes >= 1) are integers and
+must match the counts of the oracle's contingency tables exactly; MI must be
+within the FP32 tolerance of the FP64 oracle (1e-5 bits for tables of up to
+64 cells, growing with the number of cells for larger tables: each cell adds
+a few roundings to a sum), and in the FP64 mode within 1e-12 bits plus the
+rounding of the output to FP32 (half an ulp).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_19702_amd import mi, synth
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def fp32_tol(la, lb):
+    return 1e-5 * max(1.0, (la * lb) / 64.0)
+
+
+def _run(X, levels, v=None, **kw):
+    v = len(levels) if v is None else v
+    out = torch.full((v, v), float("nan"), device=DEV)
+    mi.mi_all_pairs_categorical(X, levels, out=out, v=v, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _indicator_gram(Xh, levels):
+    """Exact int64 Gram of the indicator columns (codes 1 .. L-1), and offsets."""
+    cols, off = [], [0]
+    for j, L in enumerate(levels):
+        for c in range(1, int(L)):
+            cols.append(Xh[:, j] == c)
+        off.append(off[-1] + int(L) - 1)
+    if not cols:
+        return np.zeros((0, 0), np.int64), off
+    Y = np.stack(cols, axis=1).astype(np.float64)
+    return (Y.T @ Y).astype(np.int64), off     # exact: counts < 2^53
+
+
+def fp64_tol(la, lb):
+    return 1e-12   # plus the FP32 rounding of the output, added in _compare
+
+
+def _compare(Xh, levels, got, tol_fn=fp32_tol):
+    want = oracle.cat_all_pairs(Xh, levels)
+    assert np.isfinite(got).all(), "non-finite MI"
+    assert np.array_equal(got, got.T), "MI output is not bitwise symmetric"
+    v = len(levels)
+    L = np.asarray(levels)
+    tol = np.array([[tol_fn(L[i], L[j]) for j in range(v)] for i in range(v)]) if v else np.zeros((0, 0))
+    tol = tol + np.abs(want) * 2.0 ** -24          # the output is FP32: half an ulp of rounding
+    err = np.abs(got.astype(np.float64) - want)
+    bad = err > tol
+    assert not bad.any(), f"{bad.sum()} pairs beyond tolerance, max |dMI| = {err.max()}"
+    return float(err.max()) if v else 0.0
+
+
+CASES = [  # (seed, m, v, lmin, lmax, pitch)
+    (1, 1000, 37, 1, 9, None),
+    (2, 4097, 64, 2, 3, None),
+    (3, 777, 129, 2, 6, 160),        # pitched
+    (4, 2500, 50, 2, 16, 53),        # unaligned pitch, up to 256-cell tables
+    (5, 65, 200, 2, 4, None),        # several indicator tiles, few rows
+    (6, 1, 9, 1, 5, None),           # one row
+]
+
+
+@pytest.mark.parametrize("seed,m,v,lmin,lmax,pitch", CASES)
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_categorical_matches_oracle(seed, m, v, lmin, lmax, pitch, epi):
+    say(f"[cat] seed={seed} {m}x{v} L={lmin}..{lmax} pitch={pitch} epi={epi}")
+    spec = synth.spec_categorical(seed, m, v, lmin, lmax, ldx=pitch, planted=v // 10)
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    got = _run(X[:, :v] if pitch else X, levels, epilogue=epi)
+    tol = fp64_tol if epi == 2 else fp32_tol   # the fallback mode is FP32 above tau
+    err = _compare(X.cpu().numpy()[:, :v], levels, got, tol)
+    say(f"[cat]   max |dMI| = {err:.3e}")
+
+
+def test_categorical_fallback_small_values_are_fp64():
+    say("[cat] FP64 fallback below tau")
+    spec = synth.spec_categorical(11, 3000, 40, 2, 5)
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    f64 = _run(X, levels, epilogue=2)
+    fb = _run(X, levels, epilogue=1, fallback_tau=0.05)
+    small = fb < 0.05
+    assert small.any()
+    assert np.array_equal(fb[small], f64[small]), "fallback values below tau differ from the FP64 mode"
+
+
+def test_categorical_counts_and_sums_exact():
+    say("[cat] indicator counts and sums")
+    spec = synth.spec_categorical(12, 3001, 45, 1, 7, planted=4)
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    N = mi.mi_cat_indicators(levels)
+    G = torch.full((N, N), -1, dtype=torch.int32, device=DEV)
+    S = torch.full((max(N, 1),), -1, dtype=torch.int32, device=DEV)
+    got = _run(X, levels, counts_out=G, sums_out=S)
+    Xh = X.cpu().numpy()
+    want_G, off = _indicator_gram(Xh, levels)
+    assert off[-1] == N
+    assert np.array_equal(G.cpu().numpy().astype(np.int64), want_G), "indicator counts differ"
+    assert np.array_equal(S.cpu().numpy()[:N].astype(np.int64), np.diag(want_G)), "indicator sums differ"
+    # each count is a cell of the oracle's contingency table
+    for a, b in ((0, 1), (3, 3), (7, 30), (44, 2)):
+        t = oracle.cat_table(Xh, levels, a, b)
+        assert np.array_equal(want_G[off[a]:off[a + 1], off[b]:off[b + 1]], t[1:, 1:])
+    _compare(Xh, levels, got)
+    # with counts_out given the same MI comes out (full Gram written vs upper half only)
+    assert np.array_equal(got, _run(X, levels))
+
+
+def test_categorical_binary_levels_equal_binary_counts():
+    say("[cat] levels all 2: the indicator matrix is X")
+    spec = synth.spec_random(13, 5000, 300, 0.01, 0.6, planted=6)
+    X = synth.generate(spec, device=DEV)
+    levels = [2] * 300
+    G = torch.empty((300, 300), dtype=torch.int32, device=DEV)
+    got = _run(X, levels, counts_out=G)
+    n11 = torch.empty((300, 300), dtype=torch.int32, device=DEV)
+    out_b = torch.empty((300, 300), device=DEV)
+    mi.mi_all_pairs_ex(X, out=out_b, n11_out=n11)
+    torch.cuda.synchronize()
+    assert torch.equal(G, n11), "indicator counts differ from the binary path's n11"
+    assert np.abs(got.astype(np.float64) - out_b.cpu().numpy().astype(np.float64)).max() <= 2e-5
+    _compare(X.cpu().numpy(), levels, got)
+
+
+@pytest.mark.parametrize("tile,splits", [(1, 1), (2, 1), (1, 3), (2, 7)])
+def test_categorical_configurations_bitwise_equal(tile, splits):
+    say(f"[cat] tile={tile} splits={splits}")
+    spec = synth.spec_categorical(14, 20_000, 120, 2, 5, planted=5)
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    base = _run(X, levels)
+    assert np.array_equal(_run(X, levels, tile=tile, splits=splits), base)
+
+
+def test_categorical_degenerate_shapes():
+    say("[cat] v = 0, single variable, all levels 1, 256 levels")
+    X = torch.zeros((10, 4), dtype=torch.uint8, device=DEV)
+    out = torch.empty((0, 0), device=DEV)
+    mi.mi_all_pairs_categorical(X, [], out=out, v=0)
+    got = _run(X, [1, 1, 1, 1])
+    assert (got == 0).all(), got
+    spec = synth.spec_categorical(15, 5000, 3, levels=[256, 256, 2], alpha=5.0, planted=1)
+    Xc = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    _compare(Xc.cpu().numpy(), levels, _run(Xc, levels))
+    one = synth.spec_categorical(16, 999, 1, 4, 4)
+    Xo = synth.cat_generate(one, device=DEV)
+    _compare(Xo.cpu().numpy(), [4], _run(Xo, [4]))
+
+
+def test_categorical_validate():
+    say("[cat] validate rejects a code past its level count")
+    spec = synth.spec_categorical(17, 400, 20, 2, 6)
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    ok = _run(X, levels, validate=True)
+    _compare(X.cpu().numpy(), levels, ok)
+    Xb = X.clone()
+    Xb[123, 7] = levels[7]
+    with pytest.raises(mi.MIError) as e:
+        _run(Xb, levels, validate=True)
+    assert e.value.status == 10
+    with pytest.raises(mi.MIError):
+        _run(X, levels[:-1] + [0])          # a level count below 1
+    with pytest.raises(mi.MIError):
+        _run(X, levels[:-1] + [257])        # above 256
+
+
+def test_categorical_side_stream():
+    say("[cat] on a side stream")
+    spec = synth.spec_categorical(18, 3000, 70, 2, 4)
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    s = torch.cuda.Stream()
+    out = torch.empty((70, 70), device=DEV)
+    with torch.cuda.stream(s):
+        mi.mi_all_pairs_categorical(X, levels, out=out, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), _run(X, levels))
+
+
+def test_genotype_workload_sampled():
+    """The full-size genotype workload (1,000,000 x 2,048, 3 codes) in the
+    configuration the benchmark times; sampled pairs against the oracle."""
+    spec = synth.spec_genotypes()
+    say(f"[cat] genotypes {spec.m}x{spec.v}")
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    got = _run(X, levels)
+    rng = np.random.default_rng(19)
+    cols = sorted(set(rng.choice(spec.v, size=10, replace=False).tolist()) |
+                  {spec.planted[0][0], spec.planted[0][1]})
+    sub = synth.cat_columns(spec, cols).numpy()
+    want = oracle.cat_all_pairs(sub, [levels[c] for c in cols])
+    err = np.abs(got[np.ix_(cols, cols)].astype(np.float64) - want).max()
+    say(f"[cat]   sampled max |dMI| = {err:.3e}")
+    assert err <= 1e-5
+    assert np.array_equal(got, got.T)
+    d, s_, _q = spec.planted[0]
+    assert got[d, s_] > 10 * np.median(got[d]), "planted pair does not stand out"
