@@ -226,6 +226,36 @@ def bench_sparse_input(dev, densities=(0.001, 0.005, 0.02), reps: int = 3):
     return {"workload": "1000000x4096, p_j ~ U[0, 2d]", "rows": res}
 
 
+def bench_categorical(dev, reps: int = 5):
+    """Categorical (genotype-like, 3 codes per column) all-pairs MI: blocking
+    call time, which covers the indicator expansion, the counts-only Gram of
+    the N = 2 v indicator columns and the per-pair contingency reduce."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    res = []
+    for m, v in ((1_000_000, 2048), (100_000, 8192)):
+        spec = synth.spec_genotypes(m=m, v=v)
+        X = synth.cat_generate(spec, device=dev)
+        levels = [int(x) for x in spec.levels]
+        out = torch.empty((v, v), dtype=torch.float32, device=dev)
+        mi.mi_all_pairs_categorical(X, levels, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mi.mi_all_pairs_categorical(X, levels, out=out)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        N = mi.mi_cat_indicators(levels)
+        row = {"workload": f"genotypes_{m}x{v}", "levels": 3, "indicator_columns": N, "ms": t * 1e3,
+               "variable_pairs_per_s": v * (v + 1) / 2 / t,
+               "gram_int8_ops_per_s": 2.0 * m * N * (N + 1) / 2 / t}
+        res.append(row)
+        print(f"[categorical] {row}", file=sys.stderr, flush=True)
+        del X, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_batched(dev, reps: int = 3):
     """256 independent datasets: one persistent launch vs a replayed hipGraph
     of plain launches vs 256 sequential plain calls (same results, bitwise)."""
@@ -333,6 +363,25 @@ def bench_served(dev, count: int = 300, loads=(0.5, 0.8, 0.95, 1.5), slots: int 
     return res
 
 
+def run_extras(dev, extras, args) -> dict:
+    rec = {}
+    if "configs" in extras:
+        rec["configs"] = [bench_plain(dev, "small_1000x200"), bench_plain(dev, "mid_100000x1024"),
+                          bench_plain(dev, "mid_100000x1024", tune=True), bench_plain(dev, "outbound_2000x8192"),
+                          bench_plain(dev, "outbound_2000x8192", tune=True)]
+    if "batched" in extras:
+        rec["batched"] = bench_batched(dev)
+    if "served" in extras:
+        rec["served"] = bench_served(dev, slots=args.served_slots)
+    if "sparse" in extras:
+        rec["sparse"] = bench_sparse(dev)
+    if "sparse_input" in extras:
+        rec["sparse_input"] = bench_sparse_input(dev)
+    if "categorical" in extras:
+        rec["categorical"] = bench_categorical(dev)
+    return rec
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,10 +396,13 @@ def main() -> int:
     ap.add_argument("--tile", type=int, default=0, help="force a tile config (1: 128, 2: 256)")
     ap.add_argument("--splits", type=int, default=0, help="force the K-split count")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra measurements")
-    ap.add_argument("--extras", default="configs,batched,served,sparse,sparse_input",
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the extra measurements named by --extras (no headline line)")
+    ap.add_argument("--extras", default="configs,batched,served,sparse,sparse_input,categorical",
                     help="comma list of extra measurements: configs (the 1000 x 200 and 100000 x 1024 "
                          "workloads), batched (256 datasets), served (Poisson request trace), sparse (threshold "
-                         "output on 20000 x 32768)")
+                         "output on 20000 x 32768), sparse_input (sparse-input path at 1000000 x 4096), "
+                         "categorical (genotype-like 3-code data)")
     ap.add_argument("--served-slots", type=int, default=3, help="server slots (streams) in the served measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB per step "
@@ -377,6 +429,9 @@ def main() -> int:
             torch.add(src, 0, out=dst)  # one elementwise kernel: reads nbytes, writes nbytes
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": args.warmup + args.steps}), flush=True)
+        return 0
+    if args.extras_only:
+        print(json.dumps({"extras": run_extras(dev, set(args.extras.split(",")), args)}), flush=True)
         return 0
     if args.shape:
         sm, sn = (int(v) for v in args.shape.split(","))
@@ -445,18 +500,7 @@ def main() -> int:
     del X
     torch.cuda.empty_cache()
     extras = set() if (args.no_extras or args.shape) else set(args.extras.split(","))
-    if "configs" in extras:
-        rec["configs"] = [bench_plain(dev, "small_1000x200"), bench_plain(dev, "mid_100000x1024"),
-                          bench_plain(dev, "mid_100000x1024", tune=True), bench_plain(dev, "outbound_2000x8192"),
-                          bench_plain(dev, "outbound_2000x8192", tune=True)]
-    if "batched" in extras:
-        rec["batched"] = bench_batched(dev)
-    if "served" in extras:
-        rec["served"] = bench_served(dev, slots=args.served_slots)
-    if "sparse" in extras:
-        rec["sparse"] = bench_sparse(dev)
-    if "sparse_input" in extras:
-        rec["sparse_input"] = bench_sparse_input(dev)
+    rec.update(run_extras(dev, extras, args))
     if args.cpu_seconds > 0:
         rec["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(rec), flush=True)

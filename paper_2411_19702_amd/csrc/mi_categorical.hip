@@ -35,7 +35,7 @@ namespace {
 // A column of the indicator matrix is described by (variable << 9) | code.
 constexpr int32_t kCodeBits = 9;
 constexpr int32_t kCodeMask = (1 << kCodeBits) - 1;
-constexpr int32_t kPadEntry = 256;  // variable 0, code 256: matches no byte (padding columns)
+constexpr int32_t kPadEntry = 256;  // code 256 of variable 0: matches no byte (padding columns)
 constexpr int kTile = 32;           // reduce: 32 x 32 variable pairs per block
 constexpr int64_t kMaxVars = (int64_t)65535 * kTile;
 
@@ -46,30 +46,92 @@ __device__ __forceinline__ uint32_t indicator(const uint8_t* __restrict__ xr, in
   return (uint32_t)xr[e >> kCodeBits] == (uint32_t)(e & kCodeMask) ? 1u : 0u;
 }
 
+// 0x01 in every byte where a and b agree, 0x00 elsewhere (exact: the adds
+// cannot carry across bytes).
+__device__ __forceinline__ uint32_t eq_bytes(uint32_t a, uint32_t b) {
+  const uint32_t t = a ^ b;
+  return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t | 0x7F7F7F7Fu) >> 7;
+}
+
 // 1. Y[r][k] = (X[r][var(k)] == code(k)); padding columns up to the pitch are
-//    0.  A thread writes one 16-byte chunk of a row (16 indicator columns,
-//    their descriptors read as four 16-byte loads); a block covers `rpb`
-//    whole rows per iteration, so small N still fills the block.
+//    0.  A thread owns one 16-byte chunk (16 indicator columns) for a run of
+//    rows, so its column descriptors are decoded once.  The chunk's
+//    variables are consecutive bytes of the row (each variable has at least
+//    one indicator column unless it has a single level), at most 16 of them:
+//    the thread loads the 32-byte window from its 16-byte-aligned start
+//    (two 16-byte loads), picks each output dword's 4 source bytes from two
+//    adjacent window dwords with one byte permute, and compares all 4 codes
+//    at once.  Chunks whose variables do not fit that window (single-level
+//    variables leave gaps) and unaligned layouts load byte by byte.
 __global__ __launch_bounds__(256) void k_cat_expand(const uint8_t* __restrict__ X, int64_t ldx, int64_t m,
-                                                    const int32_t* __restrict__ colmap, int32_t cpr, int32_t rpb,
+                                                    const int32_t* __restrict__ colmap, int32_t cpr, int32_t cg,
+                                                    int64_t rows_per_block, int32_t aligned,
                                                     uint8_t* __restrict__ Y, int64_t ldy) {
-  const int32_t items = rpb * cpr;
-  for (int64_t r0 = (int64_t)blockIdx.x * rpb; r0 < m; r0 += (int64_t)gridDim.x * rpb) {
-    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
-      const int32_t rr = it / cpr, ch = it - rr * cpr;
-      const int64_t r = r0 + rr;
-      if (r >= m) break;  // items run in row order: the rest are past m too
-      const uint8_t* xr = X + r * ldx;
-      const int4* cm = reinterpret_cast<const int4*>(colmap) + (int64_t)ch * 4;
-      uint32_t w[4];
+  const int tc = threadIdx.x % cg, tr = threadIdx.x / cg, rstep = blockDim.x / cg;
+  const int32_t ch = blockIdx.y * cg + tc;
+  if (ch >= cpr) return;  // no barriers below
+  int32_t ent[16];
+  const int4* cm = reinterpret_cast<const int4*>(colmap) + (int64_t)ch * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int4 e = cm[q];
+    ent[4 * q] = e.x;
+    ent[4 * q + 1] = e.y;
+    ent[4 * q + 2] = e.z;
+    ent[4 * q + 3] = e.w;
+  }
+  // Window start (the first column of a chunk is never padding).
+  const int32_t base = (ent[0] >> kCodeBits) & ~15;
+  int dq[4];
+  uint32_t selq[4], codeq[4];
+  bool fast = aligned != 0, second = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int32_t f = ent[4 * q];
+    dq[q] = (f & kCodeMask) == kPadEntry ? 0 : ((f >> kCodeBits) - base) >> 2;
+    if (dq[q] > 6) fast = false;
+    uint32_t sel = 0, code = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int32_t e = ent[4 * q + t];
+      const bool pad = (e & kCodeMask) == kPadEntry;
+      const int32_t off = (e >> kCodeBits) - base;  // byte of the window
+      const int32_t b = off - 4 * dq[q];            // byte of the dword pair
+      if (!pad && (b < 0 || b > 7)) fast = false;
+      if (!pad && off >= 16) second = true;         // then base + 32 <= ldx (aligned layout)
+      sel |= (pad ? 0x0Cu : (uint32_t)b) << (8 * t);  // permute selector 0x0C yields 0x00
+      code |= (pad ? 0xFFu : (uint32_t)(e & 0xFF)) << (8 * t);
+    }
+    selq[q] = sel;
+    codeq[q] = code;
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < m ? r0 + rows_per_block : m;
+  for (int64_t r = r0 + tr; r < r1; r += rstep) {
+    uint32_t o[4];
+    if (fast) {
+      const uint8_t* xw = X + r * ldx + base;
+      const uint4 a = *reinterpret_cast<const uint4*>(xw);
+      const uint4 b = second ? *reinterpret_cast<const uint4*>(xw + 16) : make_uint4(0, 0, 0, 0);
+      const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int4 e = cm[q];
-        w[q] = indicator(xr, e.x) | (indicator(xr, e.y) << 8) | (indicator(xr, e.z) << 16) |
-               (indicator(xr, e.w) << 24);
+        uint32_t lo = w[0], hi = w[1];
+#pragma unroll
+        for (int k = 1; k < 7; ++k) {
+          lo = dq[q] == k ? w[k] : lo;
+          hi = dq[q] == k ? w[k + 1] : hi;
+        }
+        o[q] = eq_bytes(__builtin_amdgcn_perm(hi, lo, selq[q]), codeq[q]);
       }
-      *reinterpret_cast<uint4*>(Y + r * ldy + (int64_t)ch * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+    } else {
+      const uint8_t* xr = X + r * ldx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        o[q] = indicator(xr, ent[4 * q]) | (indicator(xr, ent[4 * q + 1]) << 8) |
+               (indicator(xr, ent[4 * q + 2]) << 16) | (indicator(xr, ent[4 * q + 3]) << 24);
     }
+    *reinterpret_cast<uint4*>(Y + r * ldy + (int64_t)ch * 16) = make_uint4(o[0], o[1], o[2], o[3]);
   }
 }
 
@@ -319,9 +381,13 @@ mi_status run_categorical(const mi_cat_problem* p, hipStream_t st) {
     if (s != MI_OK) return s;
     uint8_t* Y = (uint8_t*)ybuf;
     const int32_t cpr = (int32_t)(ldy / 16);
-    const int32_t rpb = std::max<int32_t>(1, 2048 / cpr);
-    const unsigned eb = (unsigned)std::min<int64_t>(cdiv(m, rpb), 65536);
-    hipLaunchKernelGGL(k_cat_expand, dim3(eb), dim3(256), 0, st, p->X, ldx, m, d_map, cpr, rpb, Y, ldy);
+    int32_t cg = 1;  // chunks per block row: up to 64, the rest of the 256 threads take more rows
+    while (cg < 64 && cg < cpr) cg *= 2;
+    const int64_t rows_per_block = 256;
+    const dim3 eg((unsigned)cdiv(m, rows_per_block), (unsigned)cdiv(cpr, cg));
+    const int32_t aligned = ((uintptr_t)p->X % 16 == 0 && ldx % 16 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_cat_expand, eg, dim3(256), 0, st, p->X, ldx, m, d_map, cpr, cg, rows_per_block, aligned, Y,
+                       ldy);
     HIPCHK(hipGetLastError());
     int32_t* Gw = p->counts_out;
     if (!Gw) {
