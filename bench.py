@@ -256,6 +256,44 @@ def bench_categorical(dev, reps: int = 5):
     return res
 
 
+def bench_packed(dev, reps: int = 10):
+    """Bit-packed input on the 1,000,000 x 4,096 workload: the byte kernel,
+    the packed kernel on pre-packed input (8x fewer input bytes), and the
+    packing pass itself; the kernels are timed with HIP events on the stream."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    spec = synth.spec_large()
+    X = synth.generate(spec, device=dev)
+    n = spec.n
+    out = torch.empty((n, n), dtype=torch.float32, device=dev)
+    P = mi.mi_pack_bits(X)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_bytes = timed(lambda: mi.mi_all_pairs_ex(X, out=out))
+    t_packed = timed(lambda: mi.mi_all_pairs_ex(P, out=out, n=n, packed=True))
+    t_pack = timed(lambda: mi.mi_pack_bits(X, out=P))
+    pu = spec.m * n * (n + 1) / 2
+    row = {"workload": f"large_{spec.m}x{n}", "bytes_ms": t_bytes, "packed_ms": t_packed, "pack_pass_ms": t_pack,
+           "pack_then_packed_ms": t_pack + t_packed, "input_bytes": spec.m * n, "packed_input_bytes": P.numel(),
+           "packed_pair_updates_per_s": pu / (t_packed * 1e-3),
+           "packed_int8_frac": 2 * pu / (t_packed * 1e-3) / 5.0e15}
+    print(f"[packed] {row}", file=sys.stderr, flush=True)
+    del X, P, out
+    torch.cuda.empty_cache()
+    return row
+
+
 def bench_batched(dev, reps: int = 3):
     """256 independent datasets: one persistent launch vs a replayed hipGraph
     of plain launches vs 256 sequential plain calls (same results, bitwise)."""
@@ -379,6 +417,8 @@ def run_extras(dev, extras, args) -> dict:
         rec["sparse_input"] = bench_sparse_input(dev)
     if "categorical" in extras:
         rec["categorical"] = bench_categorical(dev)
+    if "packed" in extras:
+        rec["packed"] = bench_packed(dev)
     return rec
 
 
@@ -398,11 +438,11 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the extra measurements")
     ap.add_argument("--extras-only", action="store_true",
                     help="run only the extra measurements named by --extras (no headline line)")
-    ap.add_argument("--extras", default="configs,batched,served,sparse,sparse_input,categorical",
+    ap.add_argument("--extras", default="configs,batched,served,sparse,sparse_input,categorical,packed",
                     help="comma list of extra measurements: configs (the 1000 x 200 and 100000 x 1024 "
                          "workloads), batched (256 datasets), served (Poisson request trace), sparse (threshold "
                          "output on 20000 x 32768), sparse_input (sparse-input path at 1000000 x 4096), "
-                         "categorical (genotype-like 3-code data)")
+                         "categorical (genotype-like 3-code data), packed (bit-packed input)")
     ap.add_argument("--served-slots", type=int, default=3, help="server slots (streams) in the served measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB per step "

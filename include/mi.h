@@ -118,6 +118,13 @@ typedef struct mi_problem {
   unsigned long long* pairs_count;  /* device; required when pairs is given           */
   float pairs_threshold;            /* bits                                           */
   int32_t algo;                     /* mi_algo; batches and the server take only DENSE */
+  /* Bit-packed input: nonzero means X holds 8 columns per byte, bit k (least
+   * significant first) of byte b of a row being column 8 b + k; ldx is then
+   * the row pitch in bytes, >= ceil(n / 8) (0 means ceil(n / 8)).  The kernel
+   * reads an eighth of the bytes and unpacks them on chip; results are the
+   * same as for the byte layout.  Single calls with the dense algorithm only
+   * (not batches or the server); validate is a no-op (every bit is 0 or 1). */
+  int32_t packed;
 } mi_problem;
 
 /* Fill *p with defaults for X (m x n, ldx = n) and out: FP32 epilogue, auto config. */
@@ -197,6 +204,12 @@ void mi_cat_problem_init(mi_cat_problem* p, const uint8_t* X, int64_t m, int64_t
 mi_status mi_cat_indicators(const int32_t* levels, int64_t v, int64_t* N);
 
 mi_status mi_all_pairs_categorical(const mi_cat_problem* p, void* stream);
+
+/* Pack a 0/1 byte matrix into the bit layout of mi_problem.packed:
+ * Xp[r][b] bit k = (X[r][8 b + k] != 0) for 8 b + k < n, other bits 0.  X is
+ * m x ldx bytes (ldx >= n), Xp is m x ldp bytes (ldp >= ceil(n / 8)); both
+ * device pointers.  Asynchronous on `stream`. */
+mi_status mi_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xp, int64_t ldp, void* stream);
 
 /* Configuration the library would use for an (m, n, ldx) problem. */
 mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits);

@@ -268,8 +268,12 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   if (p->m > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "m must be <= 2^31-1 (int32 counts), got %lld", (long long)p->m);
   if (p->n < 0) return fail(MI_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)p->n);
   if (p->n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "n must be <= 2^31-1");
-  const int64_t ldx = p->ldx == 0 ? p->n : p->ldx;
-  if (ldx < p->n) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)p->n);
+  const int64_t row_bytes = p->packed ? (p->n + 7) / 8 : p->n;  // bytes of a row that hold columns
+  const int64_t ldx = p->ldx == 0 ? row_bytes : p->ldx;
+  if (ldx < row_bytes)
+    return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < %lld bytes of a row", (long long)ldx, (long long)row_bytes);
+  if (p->packed && p->algo != MI_ALGO_DENSE)
+    return fail(MI_ERR_INVALID_ARG, "packed input takes only the dense algorithm");
   if (ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) above the supported 2^24", (long long)ldx);
   if (p->n > 0 && !p->X) return fail(MI_ERR_INVALID_ARG, "X must be non-NULL when n > 0");
   if (p->n > 0 && !p->out && !p->pairs && !p->n11_out)
@@ -308,6 +312,7 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
   P.ksteps = (int32_t)pl.ksteps;
   P.kchunk = pl.kchunk;
   P.epi = (!p->out && !p->pairs) ? kEpiCounts : p->epilogue;  // counts alone: no MI evaluated
+  P.packed = p->packed ? 1 : 0;
   P.tau = p->fallback_tau > 0.0f ? p->fallback_tau : 1e-3f;
   P.splits = pl.splits;
   P.tiles_per_xcd = pl.tpx;
@@ -347,7 +352,7 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_o
   if (s != MI_OK) return s;
   if (p->pairs) HIPCHK(fill_i32(reinterpret_cast<int*>(p->pairs_count), 0, 2, st));  // 64-bit counter
   if (p->n == 0) return MI_OK;
-  if (p->validate) {
+  if (p->validate && !p->packed) {  // packed bits are 0 or 1 by construction
     s = validate_binary(p, ldx, st);
     if (s != MI_OK) return s;
   }
@@ -363,11 +368,12 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_o
   const uint8_t* X = p->X;
   int64_t ld = ldx;
   if (!aligned) {
-    ld = packed_pitch(p->n);
+    const int64_t row_bytes = p->packed ? (p->n + 7) / 8 : p->n;
+    ld = packed_pitch(row_bytes);
     void* buf = nullptr;
     s = scratch(st, 1, ws_slot, (size_t)p->m * (size_t)ld, &buf);
     if (s != MI_OK) return s;
-    HIPCHK(launch_repack(p->X, p->m, p->n, ldx, (uint8_t*)buf, ld, st));
+    HIPCHK(launch_repack(p->X, p->m, row_bytes, ldx, (uint8_t*)buf, ld, st));
     X = (const uint8_t*)buf;
   }
   void* ws = nullptr;
@@ -435,6 +441,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     if (probs[d].validate) return fail(MI_ERR_INVALID_ARG, "problem %lld: validate is not supported in batches", (long long)d);
     if (probs[d].algo != MI_ALGO_DENSE)
       return fail(MI_ERR_INVALID_ARG, "problem %lld: batches take only the dense algorithm", (long long)d);
+    if (probs[d].packed)
+      return fail(MI_ERR_INVALID_ARG, "problem %lld: batches take only the byte layout", (long long)d);
   }
   DeviceInfo di;
   s = device_info(&di);
@@ -866,6 +874,18 @@ mi_status mi_all_pairs(const uint8_t* X, int64_t m, int64_t n, float* out) {
 mi_status mi_all_pairs_batched(const mi_problem* probs, int64_t count, void* stream, int32_t mode) {
   clear_error();
   return run_batched(probs, count, (hipStream_t)stream, mode);
+}
+
+mi_status mi_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xp, int64_t ldp, void* stream) {
+  clear_error();
+  if (m < 0 || n < 0) return fail(MI_ERR_INVALID_ARG, "m and n must be >= 0");
+  if (m == 0 || n == 0) return MI_OK;
+  if (!X || !Xp) return fail(MI_ERR_INVALID_ARG, "X and Xp must be non-NULL");
+  if (ldx < n) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)n);
+  if (ldp < (n + 7) / 8) return fail(MI_ERR_INVALID_ARG, "ldp (%lld) < ceil(n / 8)", (long long)ldp);
+  if ((n + 63) / 64 > (int64_t)64 * 65535) return fail(MI_ERR_INVALID_ARG, "n too large");
+  HIPCHK(launch_pack_bits(X, m, n, ldx, Xp, ldp, (hipStream_t)stream));
+  return MI_OK;
 }
 
 mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits) {

@@ -38,6 +38,7 @@ namespace mi {
 
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 #define MI_LDS __attribute__((address_space(3)))
 
@@ -90,6 +91,7 @@ struct ProbDev {
   int32_t tiles_per_xcd;  // plain launch: tiles owned by each of the 8 XCDs
   int32_t epi;          // mi_epilogue, or kEpiCounts: counts only, no MI evaluated
   int32_t upper_only;   // nonzero: store i <= j only (no mirror writes)
+  int32_t packed;       // X holds 8 columns per byte (bit k of byte b = column 8 b + k); ldx in bytes
   float tau;
   // Sparse output: pairs i < j with MI >= thr, appended at an atomic counter
   // (stored while the count stays below cap).  pairs == nullptr: none.
@@ -230,8 +232,20 @@ struct Smem {
   float* rcp;     // 4 * BT float
 };
 
-// One work unit.
-template <class C>
+// Bit-packed input: 16 columns from 2 packed bytes (the low 16 bits of w,
+// bit k of a byte = its k-th column), one 0/1 byte per column.  Each nibble
+// is spread to one bit per byte by one multiply: its copies shifted by 0, 7,
+// 14 and 21 bits do not overlap, so nothing carries.
+__device__ __forceinline__ uint4 unpack16(uint32_t w) {
+  const uint32_t k = 0x00204081u;
+  return make_uint4(((w & 0xFu) * k) & 0x01010101u, (((w >> 4) & 0xFu) * k) & 0x01010101u,
+                    (((w >> 8) & 0xFu) * k) & 0x01010101u, (((w >> 12) & 0xFu) * k) & 0x01010101u);
+}
+
+// One work unit.  PK: X is bit-packed; each stage is loaded into registers
+// (one 8-byte load per thread, four stages ahead), unpacked to bytes and
+// written to the ring, instead of the buffer-to-LDS DMA of the byte layout.
+template <class C, bool PK = false>
 __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1, const Smem<C>& sm) {
 #if defined(__HIP_DEVICE_COMPILE__)  // device-only body (gfx950 builtins and asm)
   constexpr int BT = C::BT, FM = C::FM, FN = C::FN;
@@ -257,15 +271,30 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   // physical segment l % SEGS, which holds logical segment (l % SEGS) ^ f(row).
   int voff[C::LOADS];
   uint32_t ldsoff[C::LOADS];
+  if constexpr (!PK) {
 #pragma unroll
-  for (int i = 0; i < C::LOADS; ++i) {
-    const int R = i * C::NWAVES + wave;
-    const int panel = R / (C::REGIONS / 2);
-    const int row = (R % (C::REGIONS / 2)) * C::ROWS_PER_REGION + lane / C::SEGS;
-    const int seg = (lane % C::SEGS) ^ seg_swz<BT>(row);
-    const int col0 = (panel == 0 ? I : J) * BT;
-    voff[i] = row * (int)P.ldx + col0 + 16 * seg;
-    ldsoff[i] = (uint32_t)R * 1024u;
+    for (int i = 0; i < C::LOADS; ++i) {
+      const int R = i * C::NWAVES + wave;
+      const int panel = R / (C::REGIONS / 2);
+      const int row = (R % (C::REGIONS / 2)) * C::ROWS_PER_REGION + lane / C::SEGS;
+      const int seg = (lane % C::SEGS) ^ seg_swz<BT>(row);
+      const int col0 = (panel == 0 ? I : J) * BT;
+      voff[i] = row * (int)P.ldx + col0 + 16 * seg;
+      ldsoff[i] = (uint32_t)R * 1024u;
+    }
+  }
+  // Packed layout: thread tid owns 64 columns (8 packed bytes, 4 segments)
+  // of one row of one panel; its segments land at their swizzled places.
+  constexpr int TPR = BT / 64;  // threads per panel row
+  static_assert(2 * KT * TPR == C::NT, "one 8-byte packed piece per thread and stage");
+  int pvoff = 0;
+  uint32_t pwoff[4] = {0u, 0u, 0u, 0u};
+  if constexpr (PK) {
+    const int panel = tid / (KT * TPR), row = (tid / TPR) % KT, q = tid % TPR;
+    pvoff = row * (int)P.ldx + ((panel == 0 ? I : J) * BT) / 8 + 8 * q;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      pwoff[g] = (uint32_t)(panel * C::PANEL + row * BT + (((4 * q + g) ^ seg_swz<BT>(row)) << 4));
   }
   // Stage j of the unit starts at row k0 + j KT; its base address advances by
   // KT * ldx bytes per stage (scalar adds, no per-stage multiplies).
@@ -355,9 +384,77 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"i"(2 * C::LOADS) : "memory");
   };
 
+  const int rows = k1 - k0;
+  if constexpr (PK) {
+    // Stage j's 8 packed bytes of this thread (zeros past the unit's rows).
+    auto pload = [&](uint64_t base, int rem) -> uint2 {
+      const __amdgpu_buffer_rsrc_t rs = stage_rsrc(base, rem, ldx32);
+      const v2u v = __builtin_amdgcn_raw_buffer_load_b64(rs, pvoff, 0, 0);
+      return make_uint2(v.x, v.y);
+    };
+    // The two halves of this thread's piece (segments 0-1 and 2-3).
+    auto pstore_lo = [&](uint2 v, uint8_t* slot) {
+      *(MI_LDS uint4*)(slot + pwoff[0]) = unpack16(v.x);
+      *(MI_LDS uint4*)(slot + pwoff[1]) = unpack16(v.x >> 16);
+    };
+    auto pstore_hi = [&](uint2 v, uint8_t* slot) {
+      *(MI_LDS uint4*)(slot + pwoff[2]) = unpack16(v.y);
+      *(MI_LDS uint4*)(slot + pwoff[3]) = unpack16(v.y >> 16);
+    };
+    // Every wave's ring writes (and its own reads) done, workgroup-wide.
+    auto write_barrier = [&]() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
+    // Registers pk[j % 4] hold stage j until it is written to the ring.
+    // Stages 0 and 1 are written before the loop; step `step` writes stage
+    // step + 2 in two halves, one beside each half's MFMAs (its slot was last
+    // read two steps before), then loads stage step + 6 into the freed
+    // registers.
+    uint2 pk0 = pload(xk0, rows), pk1 = pload(xk0 + stage_bytes, rows - KT);
+    uint2 pk2 = pload(xk0 + 2 * stage_bytes, rows - 2 * KT), pk3 = pload(xk0 + 3 * stage_bytes, rows - 3 * KT);
+    pstore_lo(pk0, sm.slot[0]);
+    pstore_hi(pk0, sm.slot[0]);
+    pstore_lo(pk1, sm.slot[1]);
+    pstore_hi(pk1, sm.slot[1]);
+    pk0 = pload(xk0 + 4 * stage_bytes, rows - 4 * KT);
+    pk1 = pload(xk0 + 5 * stage_bytes, rows - 5 * KT);
+    write_barrier();
+    read_half(sm.slot[0], 0, fa0, fb0);
+    uint64_t pbase = xk0 + 6 * stage_bytes;  // stage step + 6, loaded during step `step`
+    int prem = rows - 6 * KT;
+    auto do_step_pk = [&](uint8_t* cur, uint8_t* nxt, uint8_t* ahead, uint2& reg) {
+      read_half(cur, 1, fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_half(fa0, fb0);
+      __builtin_amdgcn_sched_barrier(0);
+      pstore_lo(reg, ahead);
+      write_barrier();
+      read_half(nxt, 0, fa0, fb0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_half(fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+      pstore_hi(reg, ahead);
+      reg = pload(pbase, prem);
+      pbase += stage_bytes;
+      prem -= KT;
+    };
+    for (int step = 0; step < nsteps; step += 4) {
+      do_step_pk(sm.slot[0], sm.slot[1], sm.slot[2], pk2);
+      do_step_pk(sm.slot[1], sm.slot[2], sm.slot[3], pk3);
+      do_step_pk(sm.slot[2], sm.slot[3], sm.slot[0], pk0);
+      do_step_pk(sm.slot[3], sm.slot[0], sm.slot[1], pk1);
+#pragma unroll
+      for (int x = 0; x < SA; ++x) {
+        csA[x] = __builtin_amdgcn_udot4(pkA[x], 0x01010101u, csA[x], false);
+        pkA[x] = 0u;
+      }
+#pragma unroll
+      for (int y = 0; y < SB; ++y) {
+        csB[y] = __builtin_amdgcn_udot4(pkB[y], 0x01010101u, csB[y], false);
+        pkB[y] = 0u;
+      }
+    }
+  } else {
   // Prologue: stages 0 .. 2 in flight in slots 0 .. 2; once stage 0 is in,
   // stage 3 goes to slot 3 and the first half of stage 0 is read.
-  const int rows = k1 - k0;
   dma_stage(xk0, rows, sm.slot[0]);
   dma_stage(xk0 + stage_bytes, rows - KT, sm.slot[1]);
   dma_stage(xk0 + 2 * stage_bytes, rows - 2 * KT, sm.slot[2]);
@@ -400,6 +497,7 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       csB[y] = __builtin_amdgcn_udot4(pkB[y], 0x01010101u, csB[y], false);
       pkB[y] = 0u;
     }
+  }
   }
   // Drain the DMA of stages past the end before the ring is reused.
   asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");

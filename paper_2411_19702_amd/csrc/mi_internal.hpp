@@ -40,6 +40,8 @@ hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, ui
                          hipStream_t st);
 hipError_t launch_repack_batch(const RepackDesc* descs, int count, int64_t blocks, hipStream_t st);
 int64_t repack_blocks(int64_t m, int64_t ldy);
+hipError_t launch_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xp, int64_t ldp,
+                            hipStream_t st);
 hipError_t fill_i32(int* p, int v, int count, hipStream_t st);
 int occupancy(int cfg);
 int persistent_occupancy(int cfg);

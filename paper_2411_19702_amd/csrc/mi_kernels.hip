@@ -22,7 +22,7 @@ namespace mi {
 // spread over XCDs, or each workgroup streaming its own share of all tiles)
 // measured 1.2-1.7x slower on the 1,000,000 x 4,096 workload, whose input
 // does not fit the last-level cache.  Padding units of the grid exit at once.
-template <class C>
+template <class C, bool PK>
 __global__ __launch_bounds__(C::NT) void k_plain(ProbDev P) {
   MI_DECLARE_SMEM(C, sm);
   const int u = blockIdx.x;
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(C::NT) void k_plain(ProbDev P) {
   const int t = xcd * tpx + (local - s * tpx);
   if (t >= P.ntiles || s >= P.splits) return;  // uniform
   const int k0 = s * P.kchunk;
-  run_unit<C>(P, t, k0, min(P.m, k0 + P.kchunk), sm);
+  run_unit<C, PK>(P, t, k0, min(P.m, k0 + P.kchunk), sm);
 }
 
 // Persistent workgroups pull units of many datasets from a device queue.
@@ -128,10 +128,70 @@ __global__ __launch_bounds__(256) void k_repack_batch(const RepackDesc* __restri
   for (int64_t q = (b - d.first_block) * 256 + threadIdx.x; q < total; q += d.blocks * 256) repack_chunk(d, q);
 }
 
+// Byte -> bit packing (the layout of a packed problem).  0x01 in each
+// nonzero byte of d, then one multiply gathers byte i into bit 24 + i (the
+// shifted copies of the four bytes land on distinct bits, so nothing carries).
+__device__ __forceinline__ uint32_t nibble_of(uint32_t d) {
+  const uint32_t nz = ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u) >> 7;
+  return ((nz * 0x01020408u) >> 24) & 0xFu;
+}
+
+// One thread per (row, 64-column group): 8 packed bytes.  Blocks cover 4 rows
+// x 64 groups.  Groups that end past n, and unaligned layouts, go byte by byte.
+__global__ __launch_bounds__(256) void k_pack_bits(const uint8_t* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                                                   uint8_t* __restrict__ Xp, int64_t ldp, int32_t vec_in,
+                                                   int32_t vec_out) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int64_t g = (int64_t)blockIdx.y * 64 + threadIdx.x % 64;
+  const int64_t nbytes = (n + 7) / 8;  // packed bytes of a row that hold columns
+  if (r >= m || 8 * g >= nbytes) return;
+  const uint8_t* xr = X + r * ldx + 64 * g;
+  uint8_t* pr = Xp + r * ldp + 8 * g;
+  if (vec_in && 64 * g + 64 <= n) {
+    uint32_t o[2] = {0u, 0u};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const uint4 v = *reinterpret_cast<const uint4*>(xr + 16 * h);
+      const uint32_t b0 = nibble_of(v.x) | (nibble_of(v.y) << 4);  // packed byte 2h
+      const uint32_t b1 = nibble_of(v.z) | (nibble_of(v.w) << 4);  // packed byte 2h + 1
+      o[h >> 1] |= (b0 | (b1 << 8)) << (16 * (h & 1));
+    }
+    if (vec_out) {
+      *reinterpret_cast<uint2*>(pr) = make_uint2(o[0], o[1]);
+    } else {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) pr[b] = (uint8_t)(o[b >> 2] >> (8 * (b & 3)));
+    }
+    return;
+  }
+  const int64_t cols = n - 64 * g < 64 ? n - 64 * g : 64;
+  const int64_t bytes = nbytes - 8 * g < 8 ? nbytes - 8 * g : 8;
+  for (int64_t b = 0; b < bytes; ++b) {
+    uint32_t v = 0;
+    for (int k = 0; k < 8; ++k)
+      if (8 * b + k < cols && xr[8 * b + k] != 0) v |= 1u << k;
+    pr[b] = (uint8_t)v;
+  }
+}
+
+hipError_t launch_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xp, int64_t ldp,
+                            hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t groups = (n + 63) / 64;
+  const int32_t vec_in = ((uintptr_t)X % 16 == 0 && ldx % 16 == 0) ? 1 : 0;
+  const int32_t vec_out = ((uintptr_t)Xp % 8 == 0 && ldp % 8 == 0) ? 1 : 0;
+  const dim3 grid((unsigned)((m + 3) / 4), (unsigned)((groups + 63) / 64));
+  hipLaunchKernelGGL(k_pack_bits, grid, dim3(256), 0, st, X, ldx, m, n, Xp, ldp, vec_in, vec_out);
+  return hipGetLastError();
+}
+
 template <class C>
 static hipError_t launch_plain_c(const ProbDev& P, hipStream_t st) {
   const int64_t grid = 8LL * P.tiles_per_xcd * P.splits;
-  hipLaunchKernelGGL(k_plain<C>, dim3((unsigned)grid), dim3(C::NT), 0, st, P);
+  if (P.packed)
+    hipLaunchKernelGGL((k_plain<C, true>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
+  else
+    hipLaunchKernelGGL((k_plain<C, false>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
   return hipGetLastError();
 }
 
@@ -190,8 +250,8 @@ int cfg_threads(int cfg) { return cfg == 1 ? Cfg256::NT : Cfg128::NT; }
 
 int occupancy(int cfg) {
   int blocks = 0;
-  hipError_t e = cfg == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg256>, Cfg256::NT, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg128>, Cfg128::NT, 0);
+  hipError_t e = cfg == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg256, false>, Cfg256::NT, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg128, false>, Cfg128::NT, 0);
   if (e != hipSuccess || blocks < 1) blocks = 1;
   return blocks;
 }

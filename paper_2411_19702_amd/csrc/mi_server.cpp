@@ -336,6 +336,7 @@ mi_status mi_server_submit(mi_server* s, const mi_problem* p, uint64_t* ticket) 
   if (st != MI_OK) return st;
   if (p->validate) return mi::fail(MI_ERR_INVALID_ARG, "validate is not supported by the server");
   if (p->algo != MI_ALGO_DENSE) return mi::fail(MI_ERR_INVALID_ARG, "the server takes only the dense algorithm");
+  if (p->packed) return mi::fail(MI_ERR_INVALID_ARG, "the server takes only the byte layout");
   Req r;
   r.p = *p;
   r.bytes = request_bytes(*p, ldx);

@@ -58,6 +58,7 @@ class mi_problem(ctypes.Structure):
         ("pairs_count", ctypes.c_void_p),
         ("pairs_threshold", ctypes.c_float),
         ("algo", ctypes.c_int32),
+        ("packed", ctypes.c_int32),
     ]
 
 
@@ -120,6 +121,7 @@ def lib() -> ctypes.CDLL:
         "mi_server_destroy": (i32, [vp]),
         "mi_version": (ctypes.c_char_p, []),
         "mi_cat_problem_init": (None, [P(mi_cat_problem), vp, i64, i64, vp, vp]),
+        "mi_pack_bits": (i32, [vp, i64, i64, i64, vp, i64, vp]),
         "mi_cat_indicators": (i32, [vp, i64, P(i64)]),
         "mi_all_pairs_categorical": (i32, [P(mi_cat_problem), vp]),
     }
@@ -147,7 +149,7 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
-def _x_layout(X: torch.Tensor, n: Optional[int]) -> Tuple[int, int, int]:
+def _x_layout(X: torch.Tensor, n: Optional[int], packed: bool = False) -> Tuple[int, int, int]:
     if not isinstance(X, torch.Tensor) or X.dim() != 2:
         raise ValueError("X must be a 2-D tensor (rows x columns)")
     if not X.is_cuda:
@@ -158,6 +160,12 @@ def _x_layout(X: torch.Tensor, n: Optional[int]) -> Tuple[int, int, int]:
     if m > 1 and X.stride(1) != 1:
         raise ValueError("X rows must be contiguous (stride(1) == 1)")
     ldx = X.stride(0) if m > 1 else max(cols, 1)
+    if packed:
+        if n is None:
+            raise ValueError("a packed X needs n (its bytes hold 8 columns each)")
+        if (n + 7) // 8 > cols:
+            raise ValueError("n exceeds 8 * X.shape[1]")
+        return m, n, ldx
     n = cols if n is None else n
     if n > cols:
         raise ValueError("n exceeds X.shape[1]")
@@ -168,10 +176,10 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
                  n11_out: Optional[torch.Tensor] = None, colsum_out: Optional[torch.Tensor] = None,
                  epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3, validate: bool = False, tile: int = 0,
                  splits: int = 0, pairs: Optional[torch.Tensor] = None, pairs_count: Optional[torch.Tensor] = None,
-                 pairs_threshold: float = 0.0, algo: int = 0) -> mi_problem:
+                 pairs_threshold: float = 0.0, algo: int = 0, packed: bool = False) -> mi_problem:
     """pairs: int32 GPU tensor of shape (capacity, 3) receiving (i, j, MI bits as FP32) rows;
     pairs_count: int64 GPU tensor with one element (the number of qualifying pairs)."""
-    m, n, ldx = _x_layout(X, n)
+    m, n, ldx = _x_layout(X, n, packed)
     for name, t, dt in (("out", out, torch.float32), ("n11_out", n11_out, torch.int32),
                         ("colsum_out", colsum_out, torch.int32), ("pairs", pairs, torch.int32),
                         ("pairs_count", pairs_count, torch.int64)):
@@ -192,6 +200,7 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
     p.pairs, p.pairs_capacity = _ptr(pairs), (pairs.shape[0] if pairs is not None else 0)
     p.pairs_count, p.pairs_threshold = _ptr(pairs_count), float(pairs_threshold)
     p.algo = int(algo)
+    p.packed = 1 if packed else 0
     return p
 
 
@@ -378,4 +387,19 @@ def mi_all_pairs_categorical(X: torch.Tensor, levels, out: Optional[torch.Tensor
     p.tile, p.splits = int(tile), int(splits)
     p.counts_out, p.sums_out = _ptr(counts_out), _ptr(sums_out)
     _check(lib().mi_all_pairs_categorical(ctypes.byref(p), _stream_handle(stream)))
+    return out
+
+
+def mi_pack_bits(X: torch.Tensor, n: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    """Bit-pack a 0/1 byte matrix (m x n) into (m, ceil(n/8)) bytes, bit k of byte b = column 8b + k."""
+    m, n, ldx = _x_layout(X, n)
+    nb = (n + 7) // 8
+    if out is None:
+        out = torch.empty((m, max(nb, 1)), dtype=torch.uint8, device=X.device)
+    if not out.is_cuda or out.dtype != torch.uint8 or out.dim() != 2 or out.shape[0] != m or out.shape[1] < nb \
+            or (m > 1 and out.stride(1) != 1):
+        raise ValueError("out must be a uint8 GPU tensor of shape (m, >= ceil(n/8)) with contiguous rows")
+    ldp = out.stride(0) if m > 1 else max(out.shape[1], 1)
+    _check(lib().mi_pack_bits(X.data_ptr(), m, n, ldx, out.data_ptr(), ldp, _stream_handle(stream)))
     return out

@@ -193,3 +193,23 @@ def test_categorical_argument_checks(L):
     empty = mi.mi_cat_problem()
     L.mi_cat_problem_init(ctypes.byref(empty), None, 5, 0, None, None)
     assert L.mi_all_pairs_categorical(ctypes.byref(empty), None) == 0        # v == 0: no-op
+
+
+def test_packed_argument_checks(L):
+    """Bit-packed input: the pitch counts bytes of 8 columns; the sparse algorithm
+    and batches reject it; the packing utility checks its pitches."""
+    from paper_2411_19702_amd import mi
+    def prob(**kw):
+        p = mi.mi_problem()
+        p.X, p.m, p.n, p.out, p.packed = 16, 10, 17, 32, 1
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+    assert L.mi_all_pairs_ex(ctypes.byref(prob(ldx=2)), None) == 1               # 17 columns need 3 bytes
+    assert L.mi_all_pairs_ex(ctypes.byref(prob(ldx=3, algo=1)), None) == 1       # sparse + packed
+    arr = (mi.mi_problem * 1)(prob(ldx=3))
+    assert L.mi_all_pairs_batched(arr, 1, None, 2) == 1                          # batches: bytes only
+    assert L.mi_pack_bits(16, 10, 17, 16, 32, 3, None) == 1                      # ldx < n
+    assert L.mi_pack_bits(16, 10, 17, 17, 32, 2, None) == 1                      # ldp < ceil(n / 8)
+    assert L.mi_pack_bits(None, 10, 17, 17, 32, 3, None) == 1
+    assert L.mi_pack_bits(16, 0, 17, 17, 32, 3, None) == 0                       # empty: no-op
