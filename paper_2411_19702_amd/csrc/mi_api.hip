@@ -192,16 +192,22 @@ Plan make_plan(int64_t m, int64_t n, int cfg, int splits) {
 // slower), so the launch runs in ceil(grid / CUs) waves of units.  A unit
 // costs its rows plus, when the tile is split, about kPublishRows rows' worth
 // of time to publish its partial counts (measured: ~20 us against ~0.6 us
-// per 64-row step).  Pick the split count with the least modelled time,
-// keeping at least kMinRows rows per split.
+// per 64-row step) while the workspace of partial sums stays in the
+// last-level cache; a larger workspace sends the atomics to HBM, and the
+// cost grows with its size (fitted on 100,000 x 8,192 and 100,000 x 16,384,
+// whose workspaces are 138 MB and 545 MB: 3 and 1 splits measured best).
+// Pick the split count with the least modelled time, keeping at least
+// kMinRows rows per split.
 static int heuristic_splits(int64_t m, const Plan& p1, int cus) {
-  const int64_t kMinRows = 4096, kPublishRows = 2048;
+  const int64_t kMinRows = 4096;
+  const double ws_bytes = (double)p1.ntiles * p1.bt * p1.bt * 4.0;
+  const double kPublishRows = 2048.0 * std::max(1.0, ws_bytes / (64.0 * 1048576.0));
   const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(512, m / kMinRows));
   int best = 1;
   double best_t = 1e300;
   for (int64_t s = 1; s <= smax; ++s) {
     const double waves = std::ceil(8.0 * p1.tpx * (double)s / cus);
-    const double rows = (double)cdiv(p1.ksteps, s) * KT + (s > 1 ? (double)kPublishRows : 0.0);
+    const double rows = (double)cdiv(p1.ksteps, s) * KT + (s > 1 ? kPublishRows : 0.0);
     const double t = waves * rows;
     if (t < best_t * 0.99) {  // prefer fewer splits unless clearly faster
       best_t = t;
