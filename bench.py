@@ -450,7 +450,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: this benchmark runs on one GPU only (got --gpus {args.gpus}); "
               "the path would shard by output tiles or by rows, which is not built here", file=sys.stderr)
         return 2
 
