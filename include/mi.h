@@ -183,7 +183,8 @@ typedef struct mi_cat_problem {
   int64_t ldx;             /* row pitch in bytes, >= v; 0 means v                     */
   const int32_t* levels;   /* HOST int32[v]: level count of each variable, 1 .. 256   */
   float* out;              /* device v x v FP32 row-major, both triangles (bitwise    */
-                           /* symmetric); the diagonal holds H(X_j)                   */
+                           /* symmetric); the diagonal holds H(X_j); may be NULL when */
+                           /* `pairs` is given                                        */
   int32_t epilogue;        /* mi_epilogue                                            */
   float fallback_tau;      /* MI_EPI_FP32_FP64_FALLBACK threshold in bits; <= 0: 1e-3 */
   int32_t validate;        /* nonzero: check every code is below its level count      */
@@ -194,6 +195,13 @@ typedef struct mi_cat_problem {
   int32_t* counts_out;     /* optional device N x N int32, both triangles: the        */
                            /* indicator Gram (cells with both codes >= 1)             */
   int32_t* sums_out;       /* optional device int32[N]: indicator column sums         */
+  /* Sparse output, as in mi_problem: every pair a < b with MI >= pairs_threshold
+   * is appended to `pairs` (order unspecified), *pairs_count (device, zeroed
+   * by the call) receives their number, and out may then be NULL. */
+  mi_pair* pairs;
+  int64_t pairs_capacity;
+  unsigned long long* pairs_count;
+  float pairs_threshold;
 } mi_cat_problem;
 
 /* Fill *p with defaults (ldx = v, FP32 epilogue, library's configuration). */

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -150,8 +151,14 @@ struct CatEpi {
   const int32_t* sums;  // N indicator column sums (marginal counts of codes >= 1)
   const int32_t* off;   // v + 1: variable j's indicator columns are off[j] .. off[j + 1] - 1
   int32_t m, v;
-  float* out;           // v x v
+  float* out;           // v x v, or nullptr
   float tau;            // FP64 fallback threshold
+  // Sparse output: pairs a < b with MI >= thr, appended at an atomic counter
+  // (stored while the count stays below cap).  pairs == nullptr: none.
+  int32_t* pairs;       // cap entries of (a, b, MI as FP32 bits)
+  int64_t pairs_cap;
+  unsigned long long* pairs_count;
+  float thr;
 };
 
 __device__ __forceinline__ int32_t gram(const CatEpi& E, int p, int q) {
@@ -253,21 +260,44 @@ __global__ __launch_bounds__(256) void k_cat_reduce(CatEpi E) {
   __shared__ float tileT[kTile][kTile + 1];
   const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
   const int b = B * kTile + tx;
+  const int lane = threadIdx.x & 63;
 #pragma unroll 1
   for (int q = 0; q < kTile / 8; ++q) {
     const int al = ty + 8 * q, a = A * kTile + al;
     float val = 0.0f;
-    if (a < E.v && b < E.v && (A != B || a <= b)) {
+    const bool mine = a < E.v && b < E.v && (A != B || a <= b);
+    if (mine) {
       if (EPI == 2) {
         val = cat_pair<true>(E, a, b);
       } else {
         val = cat_pair<false>(E, a, b);
         if (EPI == 1 && val < E.tau) val = cat_pair<true>(E, a, b);
       }
-      E.out[(int64_t)a * E.v + b] = val;
+      if (E.out) E.out[(int64_t)a * E.v + b] = val;
     }
     tileT[tx][al] = val;
+    if (E.pairs) {
+      // Sparse output: one atomic per wave, lanes in order.
+      const bool keep = mine && a < b && val >= E.thr;
+      const unsigned long long mask = __ballot(keep);
+      if (mask) {  // uniform
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(E.pairs_count, (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader);
+        if (keep) {
+          const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+          if (idx < (unsigned long long)E.pairs_cap) {
+            int32_t* e3 = E.pairs + 3 * idx;
+            e3[0] = a;
+            e3[1] = b;
+            e3[2] = __float_as_int(val);
+          }
+        }
+      }
+    }
   }
+  if (!E.out) return;  // uniform: the whole block leaves, none waits at the barrier below
   __syncthreads();
 #pragma unroll 1
   for (int q = 0; q < kTile / 8; ++q) {
@@ -298,8 +328,11 @@ mi_status check_cat(const mi_cat_problem* p, int64_t* ldx_out, int64_t* N_out) {
   if (p->tile < 0 || p->tile > 2) return fail(MI_ERR_INVALID_ARG, "bad tile id %d", p->tile);
   if (p->splits < 0) return fail(MI_ERR_INVALID_ARG, "splits must be >= 0");
   int64_t N = 0;
+  if (p->pairs && (!p->pairs_count || p->pairs_capacity < 0 || !std::isfinite(p->pairs_threshold)))
+    return fail(MI_ERR_INVALID_ARG, "pairs needs pairs_count, pairs_capacity >= 0 and a finite threshold");
   if (p->v > 0) {
-    if (!p->X || !p->out || !p->levels) return fail(MI_ERR_INVALID_ARG, "X, out and levels must be non-NULL when v > 0");
+    if (!p->X || !p->levels) return fail(MI_ERR_INVALID_ARG, "X and levels must be non-NULL when v > 0");
+    if (!p->out && !p->pairs) return fail(MI_ERR_INVALID_ARG, "out or the sparse pairs output must be given");
     for (int64_t j = 0; j < p->v; ++j) {
       if (p->levels[j] < 1 || p->levels[j] > 256)
         return fail(MI_ERR_INVALID_ARG, "levels[%lld] = %d is outside 1 .. 256", (long long)j, p->levels[j]);
@@ -317,6 +350,7 @@ mi_status run_categorical(const mi_cat_problem* p, hipStream_t st) {
   int64_t ldx = 0, N = 0;
   mi_status s = check_cat(p, &ldx, &N);
   if (s != MI_OK) return s;
+  if (p->pairs) HIPCHK(fill_i32(reinterpret_cast<int*>(p->pairs_count), 0, 2, st));  // 64-bit counter
   const int64_t v = p->v, m = p->m;
   if (v == 0) return MI_OK;
   const int64_t ldy = packed_pitch(N);
@@ -417,6 +451,10 @@ mi_status run_categorical(const mi_cat_problem* p, hipStream_t st) {
   E.v = (int32_t)v;
   E.out = p->out;
   E.tau = p->fallback_tau > 0.0f ? p->fallback_tau : 1e-3f;
+  E.pairs = reinterpret_cast<int32_t*>(p->pairs);
+  E.pairs_cap = p->pairs_capacity;
+  E.pairs_count = p->pairs_count;
+  E.thr = p->pairs_threshold;
   const unsigned T = (unsigned)cdiv(v, kTile);
   const dim3 grid(T, T);
   if (p->epilogue == 2)

@@ -77,6 +77,10 @@ class mi_cat_problem(ctypes.Structure):
         ("splits", ctypes.c_int32),
         ("counts_out", ctypes.c_void_p),
         ("sums_out", ctypes.c_void_p),
+        ("pairs", ctypes.c_void_p),
+        ("pairs_capacity", ctypes.c_int64),
+        ("pairs_count", ctypes.c_void_p),
+        ("pairs_threshold", ctypes.c_float),
     ]
 
 
@@ -357,9 +361,13 @@ def mi_cat_indicators(levels) -> int:
 def mi_all_pairs_categorical(X: torch.Tensor, levels, out: Optional[torch.Tensor] = None, v: Optional[int] = None,
                              epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3, validate: bool = False,
                              tile: int = 0, splits: int = 0, counts_out: Optional[torch.Tensor] = None,
-                             sums_out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+                             sums_out: Optional[torch.Tensor] = None, stream=None,
+                             pairs: Optional[torch.Tensor] = None, pairs_count: Optional[torch.Tensor] = None,
+                             pairs_threshold: float = 0.0, dense: bool = True):
     """MI matrix (v x v FP32, bits) of categorical X: column j holds codes 0 .. levels[j]-1.
-    X is a uint8 GPU tensor (m, cols) with contiguous rows; v defaults to cols."""
+    X is a uint8 GPU tensor (m, cols) with contiguous rows; v defaults to cols.
+    pairs / pairs_count / pairs_threshold: the sparse output as in make_problem;
+    dense=False writes no matrix (returns None)."""
     if not isinstance(X, torch.Tensor) or X.dim() != 2 or not X.is_cuda or X.dtype not in (torch.uint8, torch.int8):
         raise ValueError("X must be a 2-D uint8 GPU tensor of codes")
     m, cols = X.shape
@@ -370,22 +378,27 @@ def mi_all_pairs_categorical(X: torch.Tensor, levels, out: Optional[torch.Tensor
     if v > cols:
         raise ValueError("v exceeds X.shape[1]")
     lv = _levels_array(levels, v)
-    if out is None:
+    if out is None and dense:
         out = torch.empty((v, v), dtype=torch.float32, device=X.device)
+    if pairs is not None and (pairs.dim() != 2 or pairs.shape[1] != 3 or pairs_count is None or pairs_count.numel() < 1):
+        raise ValueError("pairs must be (capacity, 3) int32 with a one-element int64 pairs_count")
     for name, t, dt in (("out", out, torch.float32), ("counts_out", counts_out, torch.int32),
-                        ("sums_out", sums_out, torch.int32)):
+                        ("sums_out", sums_out, torch.int32), ("pairs", pairs, torch.int32),
+                        ("pairs_count", pairs_count, torch.int64)):
         if t is not None and (not t.is_cuda or t.dtype != dt or not t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous {dt} GPU tensor")
     N = sum(int(x) - 1 for x in levels[:v]) if v else 0
-    if out.numel() < v * v or (counts_out is not None and counts_out.numel() < N * N) or \
+    if (out is not None and out.numel() < v * v) or (counts_out is not None and counts_out.numel() < N * N) or \
             (sums_out is not None and sums_out.numel() < N):
         raise ValueError("output tensor too small")
     p = mi_cat_problem()
-    lib().mi_cat_problem_init(ctypes.byref(p), X.data_ptr(), m, v, ctypes.cast(lv, ctypes.c_void_p), out.data_ptr())
+    lib().mi_cat_problem_init(ctypes.byref(p), X.data_ptr(), m, v, ctypes.cast(lv, ctypes.c_void_p), _ptr(out))
     p.ldx = ldx
     p.epilogue, p.fallback_tau, p.validate = int(epilogue), float(fallback_tau), 1 if validate else 0
     p.tile, p.splits = int(tile), int(splits)
     p.counts_out, p.sums_out = _ptr(counts_out), _ptr(sums_out)
+    p.pairs, p.pairs_capacity = _ptr(pairs), (pairs.shape[0] if pairs is not None else 0)
+    p.pairs_count, p.pairs_threshold = _ptr(pairs_count), float(pairs_threshold)
     _check(lib().mi_all_pairs_categorical(ctypes.byref(p), _stream_handle(stream)))
     return out
 

@@ -212,3 +212,32 @@ def test_genotype_workload_sampled():
     assert np.array_equal(got, got.T)
     d, s_, _q = spec.planted[0]
     assert got[d, s_] > 10 * np.median(got[d]), "planted pair does not stand out"
+
+
+def test_categorical_sparse_pairs_output():
+    say("[cat] threshold pairs: equal to the dense output filtered, exact count, capacity overflow")
+    spec = synth.spec_categorical(20, 4000, 150, 2, 6, planted=15)
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    dense = _run(X, levels)
+    thr = 0.02
+    iu = np.triu_indices(150, 1)
+    want = {(int(i), int(j)): dense[i, j] for i, j in zip(*iu) if dense[i, j] >= thr}
+    assert 0 < len(want) < 1000
+    for cap, with_dense in ((4096, True), (4096, False), (len(want) // 2, False)):
+        pairs = torch.full((max(cap, 1), 3), -1, dtype=torch.int32, device=DEV)
+        cnt = torch.zeros((1,), dtype=torch.int64, device=DEV)
+        out = torch.full((150, 150), float("nan"), device=DEV) if with_dense else None
+        mi.mi_all_pairs_categorical(X, levels, out=out, dense=with_dense, pairs=pairs[:cap], pairs_count=cnt,
+                                    pairs_threshold=thr)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == len(want), (int(cnt.item()), len(want))
+        got = pairs[:min(cap, len(want))].cpu().numpy()
+        seen = set()
+        for i, j, bits in got.tolist():
+            val = np.array([bits], dtype=np.int32).view(np.float32)[0]
+            assert (i, j) in want and val == want[(i, j)], (i, j, val)
+            seen.add((i, j))
+        assert len(seen) == min(cap, len(want))
+        if with_dense:
+            assert np.array_equal(out.cpu().numpy(), dense)
