@@ -102,7 +102,7 @@ def roofline(m: int, ldx: int, n: int, kernel_s: float, ops_per_s: float, traffi
     """Roofline object for the fused kernel: against the int8 matrix-core peak,
     or, for output-bound shapes (m below the crossover), against HBM with the
     algorithmic bytes (X read once + the n x n FP32 output)."""
-    kern = "mi::k_plain<mi::Cfg<%d, 2, %d, 4>>" % ((128, 2) if tile == 1 else (256, 4))
+    kern = "mi::k_plain<mi::Cfg<%d, 2, %d, 4>, false>" % ((128, 2) if tile == 1 else (256, 4))
     if m < OUTPUT_BOUND_ROWS:
         gbs = (m * ldx + 4 * n * n) / kernel_s
         return {"bound": "hbm", "achieved": gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
