@@ -34,8 +34,8 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   - Nothing is thrown across the ABI: every call returns an mi_status and
  *     mi_last_error() gives a thread-local message for the last failure.
- *   - Limits: 1 <= m <= 2^31 - 1 (int32 counts), 0 <= n <= 2^31 - 1; n == 0
- *     is a successful no-op.  Counts convert exactly to FP32 below 2^24 rows;
+ *   - Limits: 1 <= m <= 2^31 - 1 (int32 counts), 0 <= n <= 4,194,176 (32,767
+ *     column panels of 128); n == 0 is a successful no-op.  Counts convert exactly to FP32 below 2^24 rows;
  *     above that the FP32 epilogue rounds them (the FP64 modes stay exact).
  */
 #ifndef MI_H_

@@ -268,12 +268,16 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
 // -------------------------------------------------------------- arguments --
 // Rows of one 64-row stage are addressed with 32-bit offsets.
 static constexpr int64_t kMaxPitch = (int64_t)1 << 24;
+static constexpr int64_t kMaxCols = (int64_t)32767 * 128;
 mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   if (!p) return fail(MI_ERR_INVALID_ARG, "problem is NULL");
   if (p->m <= 0) return fail(MI_ERR_INVALID_ARG, "m must be >= 1 (got %lld)", (long long)p->m);
   if (p->m > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "m must be <= 2^31-1 (int32 counts), got %lld", (long long)p->m);
   if (p->n < 0) return fail(MI_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)p->n);
-  if (p->n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "n must be <= 2^31-1");
+  // Tiles are encoded as (I << 16) | J in int32, so at most 32,767 column
+  // panels of the narrowest (128-wide) tile.
+  if (p->n > kMaxCols)
+    return fail(MI_ERR_INVALID_ARG, "n must be <= %lld (got %lld)", (long long)kMaxCols, (long long)p->n);
   const int64_t row_bytes = p->packed ? (p->n + 7) / 8 : p->n;  // bytes of a row that hold columns
   const int64_t ldx = p->ldx == 0 ? row_bytes : p->ldx;
   if (ldx < row_bytes)

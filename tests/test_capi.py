@@ -213,3 +213,14 @@ def test_packed_argument_checks(L):
     assert L.mi_pack_bits(16, 10, 17, 17, 32, 2, None) == 1                      # ldp < ceil(n / 8)
     assert L.mi_pack_bits(None, 10, 17, 17, 32, 3, None) == 1
     assert L.mi_pack_bits(16, 0, 17, 17, 32, 3, None) == 0                       # empty: no-op
+
+
+def test_column_limit(L):
+    """Tile coordinates are 16-bit fields: more than 32,767 panels of 128 columns
+    is rejected before any device work (pairs-only problem, no n x n output)."""
+    from paper_2411_19702_amd import mi
+    p = mi.mi_problem()
+    p.X, p.m, p.n, p.ldx = 16, 10, 32767 * 128 + 1, 32767 * 128 + 1
+    p.pairs, p.pairs_capacity, p.pairs_count, p.pairs_threshold = 64, 4, 128, 0.5
+    assert L.mi_all_pairs_ex(ctypes.byref(p), None) == 1
+    assert b"n must be" in L.mi_last_error()
