@@ -710,7 +710,7 @@ void release_stream_resources(hipStream_t st) {
 
 // ------------------------------------------------------------------- tuner --
 mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms) {
-  if (m <= 0 || m > INT32_MAX || n <= 0 || n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "bad shape for tuning");
+  if (m <= 0 || m > INT32_MAX || n <= 0 || n > kMaxCols) return fail(MI_ERR_INVALID_ARG, "bad shape for tuning");
   if (ldx == 0) ldx = n;
   if (ldx < n || ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "bad ldx for tuning");
   DeviceInfo di;
@@ -900,7 +900,7 @@ mi_status mi_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint
 
 mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits) {
   clear_error();
-  if (m <= 0 || m > INT32_MAX || n < 0 || n > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "bad shape");
+  if (m <= 0 || m > INT32_MAX || n < 0 || n > kMaxCols) return fail(MI_ERR_INVALID_ARG, "bad shape");
   if (ldx == 0) ldx = n;
   if (ldx < n) return fail(MI_ERR_INVALID_ARG, "ldx < n");
   Plan pl;
