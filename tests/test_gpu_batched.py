@@ -121,3 +121,23 @@ def test_batched_full_recipe_256():
     cost = [s.m * s.n * s.n for s in specs]
     order = np.argsort(cost)
     _oracle_check(specs, Xs, per, idx_full=order[:4].tolist(), idx_sampled=order[-2:].tolist())
+
+
+@pytest.mark.parametrize("mode", [mi.MI_BATCH_PERSISTENT, mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL])
+def test_batched_counts_only_problems(mode):
+    """Problems with no MI output (n11 and column sums only) mixed with full ones."""
+    say(f"[batched] counts-only problems, mode {mode}")
+    specs = [synth.spec_random(600 + k, 3000 + 700 * k, 90 + 37 * k, 0.02, 0.6, planted=3) for k in range(5)]
+    Xs = [synth.generate(s, device=DEV) for s in specs]
+    outs, n11s, css = _alloc(specs)
+    probs = [mi.make_problem(X, None if k % 2 else o, n11_out=a, colsum_out=c)
+             for k, (X, o, a, c) in enumerate(zip(Xs, outs, n11s, css))]
+    mi.mi_all_pairs_batched(probs, mode=mode)
+    torch.cuda.synchronize()
+    for k, (s, X) in enumerate(zip(specs, Xs)):
+        o, a, c = _run([s], [X], mi.MI_BATCH_SEQUENTIAL)
+        assert torch.equal(n11s[k], a[0]) and torch.equal(css[k][:s.n], c[0][:s.n])
+        if k % 2 == 0:
+            assert torch.equal(outs[k], o[0])
+        else:
+            assert torch.isnan(outs[k]).all()       # untouched
