@@ -636,12 +636,11 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   auto strip_rows = [&](int i0, auto EPI) {
     constexpr int epi = decltype(EPI)::value;
     const int rows = min(32, n - i0);  // rows past n (tile padding) are skipped
-    for (int rr = 0; rr < rows; ++rr) {
-      const int il = i0 - I * BT + rr, i = i0 + rr;  // row, the same for all lanes
-      const int e = rr * WTN + lane;
-      const int v11 = sN[e];
+    // The count and MI of row rr (this lane's column).
+    auto eval = [&](int rr, int& v11, float& v) {
+      const int il = i0 - I * BT + rr;
+      v11 = sN[rr * WTN + lane];
       const int ci = sColA[il];
-      float v;
       if (epi == kEpiCounts) {
         v = 0.0f;
       } else if (epi == 2) {
@@ -650,7 +649,11 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
         v = mi_value32(P.m, ci, cj, v11, rA1[il], rA0[il], r1j, r0j, rfm);
         if (epi == 1 && v < P.tau) v = mi_value64(P.m, ci, cj, v11);
       }
-      sM[e] = v;
+    };
+    // Its strip entry (for the mirror pass), tile-row stores and sparse output.
+    auto emit = [&](int rr, int v11, float v) {
+      const int i = i0 + rr;  // row, the same for all lanes
+      sM[rr * WTN + lane] = v;
       if (i < n && j < n && (!diag || j >= i)) {
         if (P.out) P.out[i * ln + j] = v;
         if (P.n11_out) P.n11_out[i * ln + j] = v11;
@@ -675,6 +678,27 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
           }
         }
       }
+    };
+    // Two rows per iteration: their independent LDS reads and log2 chains
+    // overlap (two waves per SIMD hide little latency on their own).
+    int rr = 0;
+#pragma clang loop unroll(disable)
+    for (; rr + 1 < rows; rr += 2) {
+      int c0, c1;
+      float v0, v1;
+      eval(rr, c0, v0);
+      eval(rr + 1, c1, v1);
+      // Both rows' values exist here: keeps the compiler from sinking the
+      // second row's arithmetic past the first row's conditional stores.
+      asm volatile("" : "+v"(v0), "+v"(v1), "+v"(c0), "+v"(c1));
+      emit(rr, c0, v0);
+      emit(rr + 1, c1, v1);
+    }
+    if (rr < rows) {
+      int c0;
+      float v0;
+      eval(rr, c0, v0);
+      emit(rr, c0, v0);
     }
   };
   static_assert(FM <= 4, "the strip switch covers four accumulator blocks");
