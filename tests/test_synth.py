@@ -78,3 +78,23 @@ def test_batched_and_served_recipes():
     assert all(b > a for a, b in zip(t, t[1:]))
     for r in reqs:
         assert 1000 <= r.spec.m <= 200_000 and 128 <= r.spec.n <= 8192
+
+
+def test_categorical_generators():
+    spec = synth.spec_categorical(3, 700, 25, 1, 9, planted=3)
+    X = synth.cat_generate(spec).numpy()
+    assert X.shape == (700, 25)
+    assert (X < spec.levels[None, :]).all()
+    cols = [0, 7, 24, 3]
+    assert np.array_equal(synth.cat_columns(spec, cols).numpy(), X[:, cols])
+    assert np.array_equal(synth.cat_generate(spec).numpy(), X)          # deterministic
+    for dst, src, q in spec.planted:                                     # copies agree on most rows
+        agree = np.mean(X[:, dst] == X[:, src] % spec.levels[dst])
+        assert agree > 1 - q - 0.1, (dst, src, q, agree)
+    g = synth.spec_genotypes(m=20000, v=40)
+    G = synth.cat_generate(g).numpy()
+    assert set(np.unique(G)) <= {0, 1, 2} and (g.levels == 3).all()
+    f = g.cum[:, 0]                                                      # P(code 0) = (1 - maf)^2
+    assert np.allclose(np.mean(G == 0, axis=0), f, atol=0.02)
+    padded = synth.cat_generate(synth.spec_categorical(4, 50, 10, ldx=16)).numpy()
+    assert padded.shape == (50, 16) and (padded[:, 10:] == 0).all()
