@@ -201,3 +201,17 @@ def test_output_bound_workload_sampled(tile):
     Xs = synth.columns(spec, cols).numpy()
     err = compare_columns(Xs, cols, out, n11, cs)
     say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
+
+
+@pytest.mark.parametrize("epi", [0, 2])
+def test_rows_beyond_exact_fp32_counts(epi):
+    """m = 2^24 + 2^22 rows: the zero-count marginals and n00 exceed 2^24 and are
+    no longer exact in FP32.  The counts stay bit-exact (int32); the FP32
+    epilogue rounds them on conversion and must still be within tolerance."""
+    m, n = (1 << 24) + (1 << 22), 40
+    spec = synth.spec_random(77, m, n, 0.01, 0.2, planted=4)
+    say(f"[parity] {m}x{n} epi={epi}")
+    X = _gen(spec)
+    out, n11, cs = run_gpu(X, epilogue=epi)
+    assert ((m - cs.astype(np.int64)) > (1 << 24)).any(), "some marginal count should exceed 2^24"
+    compare_full(X.cpu().numpy(), n, out, n11, cs)
