@@ -122,8 +122,9 @@ typedef struct mi_problem {
    * significant first) of byte b of a row being column 8 b + k; ldx is then
    * the row pitch in bytes, >= ceil(n / 8) (0 means ceil(n / 8)).  The kernel
    * reads an eighth of the bytes and unpacks them on chip; results are the
-   * same as for the byte layout.  Single calls with the dense algorithm only
-   * (not batches or the server); validate is a no-op (every bit is 0 or 1). */
+   * same as for the byte layout.  Dense algorithm only; single calls and the
+   * graph / sequential batch modes (not the persistent mode or the server);
+   * validate is a no-op (every bit is 0 or 1). */
   int32_t packed;
 } mi_problem;
 

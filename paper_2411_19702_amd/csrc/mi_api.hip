@@ -278,10 +278,9 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   // panels of the narrowest (128-wide) tile.
   if (p->n > kMaxCols)
     return fail(MI_ERR_INVALID_ARG, "n must be <= %lld (got %lld)", (long long)kMaxCols, (long long)p->n);
-  const int64_t row_bytes = p->packed ? (p->n + 7) / 8 : p->n;  // bytes of a row that hold columns
-  const int64_t ldx = p->ldx == 0 ? row_bytes : p->ldx;
-  if (ldx < row_bytes)
-    return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < %lld bytes of a row", (long long)ldx, (long long)row_bytes);
+  const int64_t rb = row_bytes(*p);
+  const int64_t ldx = p->ldx == 0 ? rb : p->ldx;
+  if (ldx < rb) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < %lld bytes of a row", (long long)ldx, (long long)rb);
   if (p->packed && p->algo != MI_ALGO_DENSE)
     return fail(MI_ERR_INVALID_ARG, "packed input takes only the dense algorithm");
   if (ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) above the supported 2^24", (long long)ldx);
@@ -300,6 +299,9 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
 }
 
 bool is_aligned(const uint8_t* X, int64_t ldx) { return ((uintptr_t)X % 16 == 0) && (ldx % 16 == 0); }
+
+// Bytes of a row that hold columns: n, or ceil(n / 8) for bit-packed input.
+int64_t row_bytes(const mi_problem& p) { return p.packed ? (p.n + 7) / 8 : p.n; }
 
 ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const Plan& pl, void* ws,
                      const int32_t* tiles) {
@@ -378,12 +380,11 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_o
   const uint8_t* X = p->X;
   int64_t ld = ldx;
   if (!aligned) {
-    const int64_t row_bytes = p->packed ? (p->n + 7) / 8 : p->n;
-    ld = packed_pitch(row_bytes);
+    ld = packed_pitch(row_bytes(*p));
     void* buf = nullptr;
     s = scratch(st, 1, ws_slot, (size_t)p->m * (size_t)ld, &buf);
     if (s != MI_OK) return s;
-    HIPCHK(launch_repack(p->X, p->m, row_bytes, ldx, (uint8_t*)buf, ld, st));
+    HIPCHK(launch_repack(p->X, p->m, row_bytes(*p), ldx, (uint8_t*)buf, ld, st));
     X = (const uint8_t*)buf;
   }
   void* ws = nullptr;
@@ -429,6 +430,8 @@ static std::string batch_key(const mi_problem* probs, int64_t count, const std::
              p.epilogue, (double)p.fallback_tau, plans[d].cfg, plans[d].splits, (void*)p.pairs,
              (long long)p.pairs_capacity, (void*)p.pairs_count, (double)p.pairs_threshold);
     k += buf;
+    snprintf(buf, sizeof buf, "%d;", p.packed);
+    k += buf;
   }
   return k;
 }
@@ -451,8 +454,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     if (probs[d].validate) return fail(MI_ERR_INVALID_ARG, "problem %lld: validate is not supported in batches", (long long)d);
     if (probs[d].algo != MI_ALGO_DENSE)
       return fail(MI_ERR_INVALID_ARG, "problem %lld: batches take only the dense algorithm", (long long)d);
-    if (probs[d].packed)
-      return fail(MI_ERR_INVALID_ARG, "problem %lld: batches take only the byte layout", (long long)d);
+    if (probs[d].packed && mode == MI_BATCH_PERSISTENT)
+      return fail(MI_ERR_INVALID_ARG, "problem %lld: the persistent mode takes only the byte layout", (long long)d);
   }
   DeviceInfo di;
   s = device_info(&di);
@@ -516,7 +519,7 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     ws_total += (workspace_bytes(plans[d]) + 255) & ~(size_t)255;
     if (!aligned[d]) {
       rp_off[d] = rp_total;
-      rp_total += ((size_t)probs[d].m * (size_t)packed_pitch(probs[d].n) + 255) & ~(size_t)255;
+      rp_total += ((size_t)probs[d].m * (size_t)packed_pitch(row_bytes(probs[d])) + 255) & ~(size_t)255;
     }
   }
   void* ws = nullptr;
@@ -532,13 +535,13 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     const int32_t* tiles = tile_table(plans[d].ntp, &e);
     if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(e));
     const uint8_t* X = aligned[d] ? probs[d].X : (const uint8_t*)rp + rp_off[d];
-    const int64_t ld = aligned[d] ? ldx[d] : packed_pitch(probs[d].n);
+    const int64_t ld = aligned[d] ? ldx[d] : packed_pitch(row_bytes(probs[d]));
     P[d] = make_probdev(&probs[d], X, ld, plans[d], ws ? (char*)ws + ws_off[d] : nullptr, tiles);
   }
   auto repack_all = [&]() -> hipError_t {
     for (int64_t d = 0; d < count; ++d) {
       if (probs[d].n == 0 || aligned[d]) continue;
-      hipError_t e = launch_repack(probs[d].X, probs[d].m, probs[d].n, ldx[d], (uint8_t*)P[d].X, P[d].ldx, st);
+      hipError_t e = launch_repack(probs[d].X, probs[d].m, row_bytes(probs[d]), ldx[d], (uint8_t*)P[d].X, P[d].ldx, st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -583,7 +586,7 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
         if (probs[d].pairs) e = fill_i32(reinterpret_cast<int*>(probs[d].pairs_count), 0, 2, cap);
         if (e != hipSuccess || probs[d].n == 0) continue;
         if (!aligned[d])
-          e = launch_repack(probs[d].X, probs[d].m, probs[d].n, ldx[d], (uint8_t*)P[d].X, P[d].ldx, cap);
+          e = launch_repack(probs[d].X, probs[d].m, row_bytes(probs[d]), ldx[d], (uint8_t*)P[d].X, P[d].ldx, cap);
         if (e == hipSuccess) e = launch_plain(plans[d].cfg, P[d], cap);
       }
       if (e != hipSuccess) {

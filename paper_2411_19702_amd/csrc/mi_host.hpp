@@ -45,6 +45,7 @@ const int32_t* tile_table(int ntp, hipError_t* err);
 mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out);
 mi_status check_problem(const mi_problem* p, int64_t* ldx_out);
 bool is_aligned(const uint8_t* X, int64_t ldx);
+int64_t row_bytes(const mi_problem& p);
 ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const Plan& pl, void* ws,
                      const int32_t* tiles);
 mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out);

@@ -208,7 +208,7 @@ def test_packed_argument_checks(L):
     assert L.mi_all_pairs_ex(ctypes.byref(prob(ldx=2)), None) == 1               # 17 columns need 3 bytes
     assert L.mi_all_pairs_ex(ctypes.byref(prob(ldx=3, algo=1)), None) == 1       # sparse + packed
     arr = (mi.mi_problem * 1)(prob(ldx=3))
-    assert L.mi_all_pairs_batched(arr, 1, None, 2) == 1                          # batches: bytes only
+    assert L.mi_all_pairs_batched(arr, 1, None, 0) == 1                          # persistent mode: bytes only
     assert L.mi_pack_bits(16, 10, 17, 16, 32, 3, None) == 1                      # ldx < n
     assert L.mi_pack_bits(16, 10, 17, 17, 32, 2, None) == 1                      # ldp < ceil(n / 8)
     assert L.mi_pack_bits(None, 10, 17, 17, 32, 3, None) == 1

@@ -118,6 +118,33 @@ def test_packed_rejected_where_unsupported():
         mi.mi_all_pairs_ex(X, out=out, n=16, packed=True, algo=mi.MI_ALGO_SPARSE)
     p = mi.make_problem(X, out, n=16, packed=True)
     with pytest.raises(mi.MIError):
-        mi.mi_all_pairs_batched([p], mode=mi.MI_BATCH_SEQUENTIAL)
+        mi.mi_all_pairs_batched([p], mode=mi.MI_BATCH_PERSISTENT)
     with pytest.raises(ValueError):
         mi.mi_all_pairs_ex(X, out=out, n=17, packed=True)   # needs 3 bytes per row
+
+
+@pytest.mark.parametrize("mode", [mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL])
+def test_packed_in_batches(mode):
+    """Packed and byte problems in one graph / sequential batch: each equal to its single call."""
+    say(f"[packed] batch mode {mode}")
+    specs = [synth.spec_random(900 + k, 2000 + 900 * k, 70 + 53 * k, 0.0, 0.8, planted=3) for k in range(4)]
+    Xs = [synth.generate(s, device=DEV) for s in specs]
+    Ps = [mi.mi_pack_bits(X) for X in Xs]
+    nb = (specs[3].n + 7) // 8
+    Pu = torch.zeros((specs[3].m, nb + 3), dtype=torch.uint8, device=DEV)[:, 1:1 + nb]   # unaligned: repacked
+    mi.mi_pack_bits(Xs[3], out=Pu)
+    Ps[3] = Pu
+    outs = [torch.full((s.n, s.n), float("nan"), device=DEV) for s in specs]
+    probs = []
+    for k, (s, X, P, o) in enumerate(zip(specs, Xs, Ps, outs)):
+        probs.append(mi.make_problem(P, o, n=s.n, packed=True) if k % 2 == 0 or k == 3 else mi.make_problem(X, o))
+    for _ in range(2):   # the graph mode replays its cached graph the second time
+        for o in outs:
+            o.fill_(float("nan"))
+        mi.mi_all_pairs_batched(probs, mode=mode)
+        torch.cuda.synchronize()
+        for s, X, o in zip(specs, Xs, outs):
+            want = torch.empty_like(o)
+            mi.mi_all_pairs_ex(X, out=want)
+            torch.cuda.synchronize()
+            assert torch.equal(o, want)
