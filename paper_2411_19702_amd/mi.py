@@ -244,8 +244,12 @@ def mi_all_pairs_async(X: torch.Tensor, out: Optional[torch.Tensor] = None, stre
 
 
 def mi_all_pairs_ex(X: torch.Tensor, out: Optional[torch.Tensor] = None, n: Optional[int] = None, stream=None,
-                    **kw) -> torch.Tensor:
-    out = _new_out(X, n) if out is None else out
+                    dense: bool = True, **kw) -> Optional[torch.Tensor]:
+    """The extended call (make_problem's keywords).  out=None allocates the n x n
+    matrix unless dense=False: then no MI matrix is written (counts only with
+    n11_out / colsum_out, or the sparse pairs output), and None is returned."""
+    if out is None and dense:
+        out = _new_out(X, n)
     p = make_problem(X, out, n=n, **kw)
     _check(lib().mi_all_pairs_ex(ctypes.byref(p), _stream_handle(stream)))
     return out

@@ -92,7 +92,7 @@ def test_packed_unaligned_pitch_and_counts_only():
     for x, y in zip(b, p):
         assert torch.equal(x, y)
     n11 = torch.empty((333, 333), dtype=torch.int32, device=DEV)
-    mi.mi_all_pairs_ex(Pu, out=None, n=333, n11_out=n11, packed=True)
+    mi.mi_all_pairs_ex(Pu, out=None, dense=False, n=333, n11_out=n11, packed=True)
     torch.cuda.synchronize()
     assert torch.equal(n11, b[1])
 

@@ -215,3 +215,17 @@ def test_rows_beyond_exact_fp32_counts(epi):
     out, n11, cs = run_gpu(X, epilogue=epi)
     assert ((m - cs.astype(np.int64)) > (1 << 24)).any(), "some marginal count should exceed 2^24"
     compare_full(X.cpu().numpy(), n, out, n11, cs)
+
+
+def test_counts_only_call():
+    """out = NULL with n11_out: the counts alone, no MI evaluated; equal to the full call's counts."""
+    spec = synth.spec_random(91, 5000, 300, 0.0, 0.6, planted=5)
+    say("[parity] counts only 5000x300")
+    X = _gen(spec)
+    out, n11, cs = run_gpu(X)
+    n11_c = torch.full((300, 300), -1, dtype=torch.int32, device=DEV)
+    cs_c = torch.full((300,), -1, dtype=torch.int32, device=DEV)
+    r = mi.mi_all_pairs_ex(X, out=None, dense=False, n11_out=n11_c, colsum_out=cs_c)
+    torch.cuda.synchronize()
+    assert r is None
+    assert np.array_equal(n11_c.cpu().numpy(), n11) and np.array_equal(cs_c.cpu().numpy(), cs)
