@@ -15,8 +15,8 @@ Sources of truth used here:
   * textbook facts: symmetry, MI(X;X) = H(X), invariance under a relabelling
     of either variable's codes, MI(X; g(X)) = H(g(X)), the data-processing
     bound MI(X; g(Y)) <= MI(X; Y), 0 <= MI <= min(H(X), H(Y)), MI = 0 exactly
-    for a product design, and the binary case L = 2 against the binary
-    entropies.
+    for a product design, the binary case L = 2 against the binary
+    entropies, and the small-dependence limit MI -> chi^2 / (2 m ln 2).
 """
 from __future__ import annotations
 
@@ -180,6 +180,33 @@ def check_binary_case(impl, tol: float = 1e-12) -> None:
             assert abs(mi[i, j] - want) <= tol, (i, j, mi[i, j], want)
 
 
+def rows_from_table(table) -> np.ndarray:
+    """Rows (x, y) repeated table[x][y] times."""
+    t = np.asarray(table, dtype=np.int64)
+    xs, ys = np.nonzero(t >= 0)
+    reps = t[xs, ys]
+    return np.stack([np.repeat(xs, reps), np.repeat(ys, reps)], axis=1).astype(np.uint8)
+
+
+def check_small_dependence(impl) -> None:
+    """Weak dependence: MI -> chi^2 / (2 m ln 2), chi^2 = sum (n - E)^2 / E over
+    the cells, for a table whose deviations from independence sum to zero in
+    every row and column; the relative gap shrinks with the deviation."""
+    r = np.array([300_000, 200_000, 500_000])          # row marginals (m = 1,000,000)
+    c = np.array([250_000, 250_000, 500_000])          # column marginals
+    m = int(r.sum())
+    E = np.outer(r, c) // m                             # exact: products divisible by m
+    pattern = np.array([[1, -1, 0], [-1, 2, -1], [0, -1, 1]])  # zero row and column sums
+    for d in (20, 60, 200):
+        table = E + d * pattern
+        X = rows_from_table(table)
+        mi = float(np.asarray(impl(X, [3, 3]), dtype=np.float64)[0, 1])
+        chi2 = float(((table - E) ** 2 / E).sum())
+        approx = chi2 / (2 * m * math.log(2))
+        rel = abs(mi - approx) / approx
+        assert rel < 1e-2, (d, mi, approx, rel)
+
+
 def random_case(seed: int, m: int, levels):
     """Codes with skewed level frequencies and some dependent columns."""
     rng = np.random.default_rng(seed)
@@ -203,6 +230,7 @@ def run_all(impl) -> None:
     check_data_processing(impl)
     check_relabel_invariance(impl)
     check_binary_case(impl)
+    check_small_dependence(impl)
     levels = [2, 3, 4, 5, 3, 9, 2, 16, 6]
     check_identities(impl, random_case(26, 257, levels), levels)
     check_brute_force(impl)

@@ -39,6 +39,10 @@ def test_categorical_oracle_functions_relabel_and_processing():
     pins_cat.check_data_processing(oracle_impl)
 
 
+def test_categorical_oracle_small_dependence_limit():
+    pins_cat.check_small_dependence(oracle_impl)
+
+
 def test_categorical_oracle_binary_case():
     pins_cat.check_binary_case(oracle_impl)
     rng = np.random.default_rng(27)
