@@ -294,6 +294,51 @@ def bench_packed(dev, reps: int = 10):
     return row
 
 
+def bench_library_gemm(dev, reps: int = 10):
+    """Context, not the product: the vendor int8 GEMM (torch._int_mm, which
+    calls hipBLASLt on ROCm) computing the full square X^T X of the same
+    matrix, beside this library's call that computes only i <= j and also
+    produces the column sums and MI.  Both are timed with HIP events on the
+    current stream; the library GEMM's operands are contiguous (X^T is
+    materialised once, outside the timed region)."""
+    import torch
+    from paper_2411_19702_amd import mi, synth
+    res = []
+    for spec in (synth.spec_mid(), synth.spec_large()):
+        X = synth.generate(spec, device=dev)
+        m, n = spec.m, spec.n
+        assert X.shape == (m, n) and X.is_contiguous()
+        A = X.view(torch.int8).t().contiguous()
+        B = X.view(torch.int8)
+        out = torch.empty((n, n), dtype=torch.float32, device=dev)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        t_lib = timed(lambda: torch._int_mm(A, B))
+        t_mi = timed(lambda: mi.mi_all_pairs_ex(X, out=out))
+        full_ops = 2.0 * m * n * n
+        tri_ops = 2.0 * m * n * (n + 1) / 2
+        row = {"workload": f"{spec.name}", "library_gemm_ms": t_lib,
+               "library_gemm_full_square_ops_per_s": full_ops / (t_lib * 1e-3),
+               "library_gemm_int8_frac": full_ops / (t_lib * 1e-3) / 5.0e15,
+               "mi_all_pairs_ms": t_mi, "mi_all_pairs_int8_frac": tri_ops / (t_mi * 1e-3) / 5.0e15,
+               "speedup_vs_library_gemm": t_lib / t_mi}
+        print(f"[library_gemm] {row}", file=sys.stderr, flush=True)
+        res.append(row)
+        del X, A, B, out
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_batched(dev, reps: int = 3):
     """256 independent datasets: one persistent launch vs a replayed hipGraph
     of plain launches vs 256 sequential plain calls (same results, bitwise)."""
@@ -419,6 +464,8 @@ def run_extras(dev, extras, args) -> dict:
         rec["categorical"] = bench_categorical(dev)
     if "packed" in extras:
         rec["packed"] = bench_packed(dev)
+    if "library_gemm" in extras:
+        rec["library_gemm"] = bench_library_gemm(dev)
     return rec
 
 
@@ -438,11 +485,12 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the extra measurements")
     ap.add_argument("--extras-only", action="store_true",
                     help="run only the extra measurements named by --extras (no headline line)")
-    ap.add_argument("--extras", default="configs,batched,served,sparse,sparse_input,categorical,packed",
+    ap.add_argument("--extras", default="configs,batched,served,sparse,sparse_input,categorical,packed,library_gemm",
                     help="comma list of extra measurements: configs (the 1000 x 200 and 100000 x 1024 "
                          "workloads), batched (256 datasets), served (Poisson request trace), sparse (threshold "
                          "output on 20000 x 32768), sparse_input (sparse-input path at 1000000 x 4096), "
-                         "categorical (genotype-like 3-code data), packed (bit-packed input)")
+                         "categorical (genotype-like 3-code data), packed (bit-packed input), library_gemm (the "
+                         "vendor int8 GEMM of the full square X^T X, for context)")
     ap.add_argument("--served-slots", type=int, default=3, help="server slots (streams) in the served measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run a plain device copy of MIB MiB per step "
