@@ -1,15 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: all-pairs binary mutual information on one MI355X.
 
-One step = one full pass of the hot path (mi_all_pairs_async through the C
-ABI: Gram on int8 matrix cores, fused column sums and MI epilogue, tile and
-mirror write-back) over the 1,000,000 x 4,096 synthetic fingerprint-like
-matrix, already resident in HBM.
+One step = one full pass of the hot path (mi_all_pairs_ex through the C ABI
+with the library's choices: at this shape the byte matrix is converted to FP4
+(E2M1) codes, then the fused kernel runs the Gram on the FP4 matrix cores,
+with the column sums, the MI epilogue and the tile and mirror write-back)
+over the 1,000,000 x 4,096 synthetic fingerprint-like matrix, already
+resident in HBM.  --gram int8 runs the int8 Gram on the bytes instead.
 
 Prints one JSON line:
   value      pair-updates/s = m * n (n + 1) / 2 per step / seconds per step
-  roofline   the fused kernel against the int8 matrix-core peak (2 ops per
-             pair-update per row), timed with HIP events on its own stream
+             (conversion pass included)
+  roofline   the fused kernel (the dominant one) against the matrix-core peak
+             of its operand type (2 ops per pair-update per row), timed alone
+             with HIP events on its stream
   cpu_baseline  the CPU oracle on a bounded column sample of the same matrix
 """
 from __future__ import annotations
@@ -25,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT8_OPS = 5.0e15      # MI355X dense int8 matrix-core peak, ops/s
+PEAK_FP4_OPS = 10.1e15      # MI355X dense FP4 (E2M1) matrix-core peak, ops/s
+GRAM_NAMES = {1: "int8", 2: "fp4"}
 PEAK_HBM = 8.0e12           # bytes/s
 
 WORKLOADS = {
@@ -50,9 +56,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, tile: int, splits: int):
+def plain_kernel_name(tile: int, gram: int) -> str:
+    """Demangled name of the fused kernel for a tile id and Gram (input layout 0: bytes, 2: FP4)."""
+    return "mi::k_plain<mi::Cfg<%d, 2, %d, 4>, %d>" % (((128, 2) if tile == 1 else (256, 4)) + (2 if gram == 2 else 0,))
+
+
+def load_traffic(workload: str, tile: int, splits: int, kernel: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel sources with the same tile and split count."""
+    were taken on the current kernel sources for the same kernel, tile and
+    split count."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -63,7 +75,7 @@ def load_traffic(workload: str, tile: int, splits: int):
         return None
     if rec.get("kernel_hash") != kernel_source_hash():
         return None
-    if rec.get("tile") != tile or rec.get("splits") != splits:
+    if rec.get("tile") != tile or rec.get("splits") != splits or rec.get("kernel") != kernel:
         return None
     return rec.get("bytes_per_launch")
 
@@ -98,17 +110,19 @@ def cpu_baseline(spec, target_s: float):
     }
 
 
-def roofline(m: int, ldx: int, n: int, kernel_s: float, ops_per_s: float, traffic, tile: int) -> dict:
-    """Roofline object for the fused kernel: against the int8 matrix-core peak,
-    or, for output-bound shapes (m below the crossover), against HBM with the
-    algorithmic bytes (X read once + the n x n FP32 output)."""
-    kern = "mi::k_plain<mi::Cfg<%d, 2, %d, 4>, false>" % ((128, 2) if tile == 1 else (256, 4))
+def roofline(m: int, in_bytes: int, n: int, kernel_s: float, ops_per_s: float, traffic, tile: int, gram: int) -> dict:
+    """Roofline object for the fused kernel: against the matrix-core peak of its
+    operand type (int8 or FP4), or, for output-bound shapes (m below the
+    crossover), against HBM with the algorithmic bytes (the kernel's input read
+    once + the n x n FP32 output)."""
+    kern = plain_kernel_name(tile, gram)
     if m < OUTPUT_BOUND_ROWS:
-        gbs = (m * ldx + 4 * n * n) / kernel_s
+        gbs = (in_bytes + 4 * n * n) / kernel_s
         return {"bound": "hbm", "achieved": gbs / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": gbs / PEAK_HBM, "traffic": traffic, "kernel": kern, "kernel_ms": kernel_s * 1e3}
-    return {"bound": "mfma", "achieved": ops_per_s / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TFLOP/s",
-            "frac": ops_per_s / PEAK_INT8_OPS, "traffic": traffic, "kernel": kern, "kernel_ms": kernel_s * 1e3}
+    peak = PEAK_FP4_OPS if gram == 2 else PEAK_INT8_OPS
+    return {"bound": "mfma", "achieved": ops_per_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": ops_per_s / peak, "traffic": traffic, "kernel": kern, "kernel_ms": kernel_s * 1e3}
 
 
 def _pct(v, q):
@@ -131,7 +145,7 @@ def bench_plain(dev, workload: str, steps: int = 30, tune: bool = False):
     if tune:
         tile, splits, best = mi.mi_tune(m, n, X.stride(0))
         tuned = {"tile": [None, 128, 256][tile], "splits": splits}
-    tile, splits = mi.mi_plan(m, n, X.stride(0))
+    tile, splits, gram = mi.mi_plan_ex(X)
     stream = torch.cuda.current_stream()
     for _ in range(3):
         mi.mi_all_pairs_ex(X, out=out, stream=stream)
@@ -154,9 +168,11 @@ def bench_plain(dev, workload: str, steps: int = 30, tune: bool = False):
     nbytes = m * X.stride(0) + 4 * n * n
     del X, out
     torch.cuda.empty_cache()
+    peak = PEAK_FP4_OPS if gram == 2 else PEAK_INT8_OPS
     return {"workload": workload, "m": m, "n": n, "tile": [None, 128, 256][tile], "splits": splits,
-            "tuned": tuned, "kernel_ms_median": k * 1e3, "call_latency_ms_median": _pct(lat, 50) * 1e3,
-            "pair_updates_per_s": pu / k, "frac_int8_peak": 2 * pu / k / PEAK_INT8_OPS,
+            "gram": GRAM_NAMES[gram], "tuned": tuned, "call_ms_median_on_stream": k * 1e3,
+            "call_latency_ms_median": _pct(lat, 50) * 1e3, "pair_updates_per_s": pu / k,
+            "frac_int8_peak": 2 * pu / k / PEAK_INT8_OPS, "frac_gram_dtype_peak": 2 * pu / k / peak,
             "hbm_algorithmic_GBps": nbytes / k / 1e9, "frac_hbm_peak": nbytes / k / PEAK_HBM}
 
 
@@ -257,9 +273,11 @@ def bench_categorical(dev, reps: int = 5):
 
 
 def bench_packed(dev, reps: int = 10):
-    """Bit-packed input on the 1,000,000 x 4,096 workload: the byte kernel,
-    the packed kernel on pre-packed input (8x fewer input bytes), and the
-    packing pass itself; the kernels are timed with HIP events on the stream."""
+    """Packed inputs on the 1,000,000 x 4,096 workload: the int8 byte kernel;
+    bit-packed input (8x fewer input bytes, int8 Gram) and its packing pass;
+    FP4 input (2x fewer bytes, FP4 Gram) and its packing pass; the byte call
+    with the FP4 Gram (conversion included).  Timed with HIP events on the
+    stream."""
     import torch
     from paper_2411_19702_amd import mi, synth
     spec = synth.spec_large()
@@ -280,16 +298,23 @@ def bench_packed(dev, reps: int = 10):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    t_bytes = timed(lambda: mi.mi_all_pairs_ex(X, out=out))
+    Q = mi.mi_pack_fp4(X)
+    t_bytes = timed(lambda: mi.mi_all_pairs_ex(X, out=out, gram=mi.MI_GRAM_INT8))
     t_packed = timed(lambda: mi.mi_all_pairs_ex(P, out=out, n=n, packed=True))
     t_pack = timed(lambda: mi.mi_pack_bits(X, out=P))
+    t_fp4 = timed(lambda: mi.mi_all_pairs_ex(Q, out=out, n=n, packed=mi.MI_INPUT_FP4))
+    t_pack4 = timed(lambda: mi.mi_pack_fp4(X, out=Q))
+    t_bytes_fp4 = timed(lambda: mi.mi_all_pairs_ex(X, out=out, gram=mi.MI_GRAM_FP4))
     pu = spec.m * n * (n + 1) / 2
     row = {"workload": f"large_{spec.m}x{n}", "bytes_ms": t_bytes, "packed_ms": t_packed, "pack_pass_ms": t_pack,
            "pack_then_packed_ms": t_pack + t_packed, "input_bytes": spec.m * n, "packed_input_bytes": P.numel(),
            "packed_pair_updates_per_s": pu / (t_packed * 1e-3),
-           "packed_int8_frac": 2 * pu / (t_packed * 1e-3) / 5.0e15}
+           "packed_int8_frac": 2 * pu / (t_packed * 1e-3) / PEAK_INT8_OPS,
+           "fp4_input_ms": t_fp4, "fp4_pack_pass_ms": t_pack4, "fp4_input_bytes": Q.numel(),
+           "bytes_fp4_gram_ms": t_bytes_fp4, "fp4_pair_updates_per_s": pu / (t_fp4 * 1e-3),
+           "fp4_frac": 2 * pu / (t_fp4 * 1e-3) / PEAK_FP4_OPS}
     print(f"[packed] {row}", file=sys.stderr, flush=True)
-    del X, P, out
+    del X, P, Q, out
     torch.cuda.empty_cache()
     return row
 
@@ -324,13 +349,15 @@ def bench_library_gemm(dev, reps: int = 10):
             return e0.elapsed_time(e1) / reps
 
         t_lib = timed(lambda: torch._int_mm(A, B))
+        t_mi8 = timed(lambda: mi.mi_all_pairs_ex(X, out=out, gram=mi.MI_GRAM_INT8))
         t_mi = timed(lambda: mi.mi_all_pairs_ex(X, out=out))
         full_ops = 2.0 * m * n * n
         tri_ops = 2.0 * m * n * (n + 1) / 2
         row = {"workload": f"{spec.name}", "library_gemm_ms": t_lib,
                "library_gemm_full_square_ops_per_s": full_ops / (t_lib * 1e-3),
                "library_gemm_int8_frac": full_ops / (t_lib * 1e-3) / 5.0e15,
-               "mi_all_pairs_ms": t_mi, "mi_all_pairs_int8_frac": tri_ops / (t_mi * 1e-3) / 5.0e15,
+               "mi_all_pairs_int8_gram_ms": t_mi8, "mi_all_pairs_int8_gram_frac": tri_ops / (t_mi8 * 1e-3) / 5.0e15,
+               "mi_all_pairs_ms": t_mi, "mi_all_pairs_gram": GRAM_NAMES[mi.mi_plan_ex(X)[2]],
                "speedup_vs_library_gemm": t_lib / t_mi}
         print(f"[library_gemm] {row}", file=sys.stderr, flush=True)
         res.append(row)
@@ -482,6 +509,8 @@ def main() -> int:
     ap.add_argument("--shape", default="", help="M,N: time a random M x N matrix instead of a named workload")
     ap.add_argument("--tile", type=int, default=0, help="force a tile config (1: 128, 2: 256)")
     ap.add_argument("--splits", type=int, default=0, help="force the K-split count")
+    ap.add_argument("--gram", default="auto", choices=("auto", "int8", "fp4"),
+                    help="matrix instructions of the Gram (auto: the library's choice)")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra measurements")
     ap.add_argument("--extras-only", action="store_true",
                     help="run only the extra measurements named by --extras (no headline line)")
@@ -535,15 +564,13 @@ def main() -> int:
     torch.cuda.synchronize()
     if args.tune:
         mi.mi_tune(m, n, n)
-    tile, splits = mi.mi_plan(m, n, X.stride(0))
-    if args.tile:
-        tile = args.tile
-    if args.splits:
-        splits = args.splits
+    gram_req = {"auto": mi.MI_GRAM_AUTO, "int8": mi.MI_GRAM_INT8, "fp4": mi.MI_GRAM_FP4}[args.gram]
+    kw = dict(epilogue=args.epilogue, tile=args.tile, splits=args.splits, gram=gram_req)
+    tile, splits, gram = mi.mi_plan_ex(X, **kw)
     stream = torch.cuda.current_stream()
 
     def step():
-        mi.mi_all_pairs_ex(X, out=out, epilogue=args.epilogue, tile=args.tile, splits=args.splits, stream=stream)
+        mi.mi_all_pairs_ex(X, out=out, stream=stream, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -557,13 +584,38 @@ def main() -> int:
         e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
-    avg_kernel_s = sum(kern_ms) / len(kern_ms) / 1e3
+    step_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    avg_step_s = sum(step_ms) / len(step_ms) / 1e3
+    # The dominant kernel alone: with the FP4 Gram a step is the conversion
+    # pass plus the fused kernel, so each is timed by itself, the fused kernel
+    # on the converted input (same kernel, plan and stream).
+    conversion = None
+    avg_kernel_s, in_bytes = avg_step_s, m * X.stride(0)
+    if gram == mi.MI_GRAM_FP4:
+        Q = mi.mi_pack_fp4(X)
+        kq = dict(kw, gram=mi.MI_GRAM_AUTO)
+
+        def timed(fn):
+            fn()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+            for e0, e1 in evs:
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+            torch.cuda.synchronize()
+            return sum(e0.elapsed_time(e1) for e0, e1 in evs) / len(evs) / 1e3
+
+        avg_kernel_s = timed(lambda: mi.mi_all_pairs_ex(Q, out=out, n=n, packed=mi.MI_INPUT_FP4, stream=stream, **kq))
+        conv_s = timed(lambda: mi.mi_pack_fp4(X, out=Q, stream=stream))
+        in_bytes = Q.numel()
+        conversion = {"kernel": "mi::k_pack_fp4", "ms": conv_s * 1e3, "bytes": m * X.stride(0) + Q.numel(),
+                      "GBps": (m * X.stride(0) + Q.numel()) / conv_s / 1e9}
+        del Q
 
     pu_per_step = m * n * (n + 1) / 2
     value = pu_per_step * args.steps / wall
     achieved = 2.0 * pu_per_step / avg_kernel_s
-    traffic = load_traffic(args.workload, [None, 128, 256][tile], splits)
+    traffic = load_traffic(args.workload, [None, 128, 256][tile], splits, plain_kernel_name(tile, gram))
     rec = {
         "metric": "MI pair-updates/s (m*n(n+1)/2) & % int8 MFMA peak; p50/p99 request latency",
         "value": value,
@@ -575,15 +627,16 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "e2m1->f32" if gram == mi.MI_GRAM_FP4 else "int8",
         "data": "synthetic",
         "config": {
             "workload": args.workload, "m": m, "n": n, "layout": "uint8 0/1 row-major, pitch %d" % X.stride(0),
             "density": "p_j log-uniform [0.001, 0.2]" if args.workload.startswith("large") else "see recipe",
             "epilogue": ["fp32", "fp32+fp64-fallback", "fp64"][args.epilogue],
-            "tile": [None, 128, 256][tile], "splits": splits,
+            "tile": [None, 128, 256][tile], "splits": splits, "gram": GRAM_NAMES[gram],
+            "conversion": conversion, "step_ms_on_stream": avg_step_s * 1e3,
         },
-        "roofline": roofline(m, X.stride(0), n, avg_kernel_s, achieved, traffic, tile),
+        "roofline": roofline(m, in_bytes, n, avg_kernel_s, achieved, traffic, tile, gram),
     }
     del X
     torch.cuda.empty_cache()

@@ -86,6 +86,27 @@ typedef enum mi_algo {
                        /* faster (at 1M x 4096 the sparse one below ~0.3% density)          */
 } mi_algo;
 
+/* Input layouts (mi_problem.packed). */
+typedef enum mi_input {
+  MI_INPUT_BYTES = 0,  /* one 0/1 byte per entry                                          */
+  MI_INPUT_BITS = 1,   /* 8 columns per byte (mi_pack_bits)                                */
+  MI_INPUT_FP4 = 2     /* 2 columns per byte as E2M1 codes: 0b0010 (1.0) or 0 (mi_pack_fp4) */
+} mi_input;
+
+/* Matrix instructions of the dense Gram (mi_problem.gram).  Both give the same
+ * exact counts, hence bitwise the same outputs; they differ in speed.  The
+ * n11 = X^T X contraction over 0/1 entries is exact with FP4 (E2M1) operands,
+ * whose 1.0 products sum to integers in the FP32 accumulator; each work unit
+ * then covers at most 2^24 rows, so every partial count is exact. */
+typedef enum mi_gram {
+  MI_GRAM_AUTO = 0,  /* the library's choice: FP4 for byte input when the Gram dominates  */
+                     /* (byte input is first converted to the FP4 layout in scratch      */
+                     /* memory, half the input's size), int8 otherwise                   */
+  MI_GRAM_INT8 = 1,  /* v_mfma_i32_32x32x32_i8 on bytes (or unpacked bits)                */
+  MI_GRAM_FP4 = 2    /* v_mfma_scale_f32_32x32x64_f8f6f4 on E2M1 codes: twice the samples */
+                     /* per byte staged and ~1.7x the int8 instruction rate               */
+} mi_gram;
+
 /* One entry of the sparse (threshold) output: MI(X_i; X_j) in bits, i < j. */
 typedef struct mi_pair {
   int32_t i, j;
@@ -118,14 +139,22 @@ typedef struct mi_problem {
   unsigned long long* pairs_count;  /* device; required when pairs is given           */
   float pairs_threshold;            /* bits                                           */
   int32_t algo;                     /* mi_algo; batches and the server take only DENSE */
-  /* Bit-packed input: nonzero means X holds 8 columns per byte, bit k (least
-   * significant first) of byte b of a row being column 8 b + k; ldx is then
-   * the row pitch in bytes, >= ceil(n / 8) (0 means ceil(n / 8)).  The kernel
-   * reads an eighth of the bytes and unpacks them on chip; results are the
-   * same as for the byte layout.  Dense algorithm only; single calls and the
-   * graph / sequential batch modes (not the persistent mode or the server);
-   * validate is a no-op (every bit is 0 or 1). */
+  /* Input layout (mi_input).  MI_INPUT_BITS: X holds 8 columns per byte, bit
+   * k (least significant first) of byte b of a row being column 8 b + k; ldx
+   * is then the row pitch in bytes, >= ceil(n / 8) (0 means ceil(n / 8)).  The
+   * kernel reads an eighth of the bytes and unpacks them on chip; validate is
+   * a no-op (every bit is 0 or 1).  MI_INPUT_FP4: X holds 2 columns per byte,
+   * column 2 c in the low nibble of byte c, each nibble 0b0010 (a one) or 0
+   * (as mi_pack_fp4 writes them; other codes give undefined counts); ldx >=
+   * ceil(n / 2), at most 2^23; validate must be 0.  Results are the same as
+   * for the byte layout.  Packed layouts take the dense algorithm only, in
+   * single calls and the graph / sequential batch modes (not the persistent
+   * mode or the server). */
   int32_t packed;
+  /* mi_gram.  MI_GRAM_FP4 needs byte or FP4 input; MI_GRAM_INT8 byte or bit
+   * input.  The persistent batch mode and the server use the int8 Gram
+   * (MI_GRAM_AUTO) and reject MI_GRAM_FP4. */
+  int32_t gram;
 } mi_problem;
 
 /* Fill *p with defaults for X (m x n, ldx = n) and out: FP32 epilogue, auto config. */
@@ -203,6 +232,10 @@ typedef struct mi_cat_problem {
   int64_t pairs_capacity;
   unsigned long long* pairs_count;
   float pairs_threshold;
+  /* mi_gram of the indicator Gram: with FP4 the indicators are expanded
+   * straight into the FP4 layout (no conversion pass).  MI_GRAM_AUTO: the
+   * library's choice from m and N, as for mi_problem. */
+  int32_t gram;
 } mi_cat_problem;
 
 /* Fill *p with defaults (ldx = v, FP32 epilogue, library's configuration). */
@@ -220,7 +253,21 @@ mi_status mi_all_pairs_categorical(const mi_cat_problem* p, void* stream);
  * device pointers.  Asynchronous on `stream`. */
 mi_status mi_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xp, int64_t ldp, void* stream);
 
-/* Configuration the library would use for an (m, n, ldx) problem. */
+/* Pack a 0/1 byte matrix into the FP4 layout of MI_INPUT_FP4: the low nibble
+ * of Xq[r][c] is 0b0010 if X[r][2 c] != 0, else 0, and the high nibble the same
+ * for X[r][2 c + 1] (0 past column n - 1).  X is m x ldx bytes (ldx >= n), Xq
+ * is m x ldq bytes (ldq >= ceil(n / 2)); bytes of Xq past ceil(n / 2) in a
+ * row are not written.  Both device pointers.  Asynchronous on `stream`. */
+mi_status mi_pack_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xq, int64_t ldq, void* stream);
+
+/* What the library would run for *p (its dense path): the tile (mi_tile), the
+ * K-split count and the Gram (MI_GRAM_INT8 or MI_GRAM_FP4; FP4 for byte input
+ * means a conversion pass first).  Checks *p like mi_all_pairs_ex, except that
+ * no output is required; launches nothing.  Any of the outputs may be NULL. */
+mi_status mi_plan_ex(const mi_problem* p, int32_t* tile, int32_t* splits, int32_t* gram);
+
+/* Configuration the library would use for an (m, n, ldx) byte problem with the
+ * int8 Gram. */
 mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits);
 
 /* Autotuner: time the candidate (tile, splits) configurations for this shape

@@ -64,6 +64,7 @@ mi_status device_info(DeviceInfo* out) {
 //   kind 0: split-K workspace.  Kernels leave it zeroed again, so it is
 //           cleared only when it is (re)allocated.
 //   kind 1: repacked copies of inputs whose layout the DMA path cannot read.
+//   kind 7: byte input converted to the FP4 layout for the FP4 Gram.
 struct WsKey {
   int dev;
   hipStream_t st;
@@ -198,10 +199,12 @@ Plan make_plan(int64_t m, int64_t n, int cfg, int splits) {
 // whose workspaces are 138 MB and 545 MB: 3 and 1 splits measured best).
 // Pick the split count with the least modelled time, keeping at least
 // kMinRows rows per split.
-static int heuristic_splits(int64_t m, const Plan& p1, int cus) {
+// With the FP4 Gram a row costs about half as much (rows_per_step_time = 2),
+// so publishing costs twice as many rows' worth.
+static int heuristic_splits(int64_t m, const Plan& p1, int cus, double rows_per_step_time = 1.0) {
   const int64_t kMinRows = 4096;
   const double ws_bytes = (double)p1.ntiles * p1.bt * p1.bt * 4.0;
-  const double kPublishRows = 2048.0 * std::max(1.0, ws_bytes / (64.0 * 1048576.0));
+  const double kPublishRows = rows_per_step_time * 2048.0 * std::max(1.0, ws_bytes / (64.0 * 1048576.0));
   const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(512, m / kMinRows));
   int best = 1;
   double best_t = 1e300;
@@ -245,13 +248,13 @@ static ShapeKey shape_key(int64_t m, int64_t n, bool aligned) {
   return k;
 }
 
-mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out) {
+mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out, bool fp4) {
   DeviceInfo di;
   mi_status s = device_info(&di);
   if (s != MI_OK) return s;
   int cfg = tile_req == MI_TILE_256 ? 1 : (tile_req == MI_TILE_128 ? 0 : -1);
   int splits = splits_req;
-  if (splits <= 0) {
+  if (splits <= 0 && !fp4) {  // tuned entries time the int8 Gram
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(shape_key(m, n, aligned));
     if (it != g_tuned.end() && (cfg < 0 || cfg == it->second.cfg)) {
@@ -260,16 +263,31 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
     }
   }
   if (cfg < 0) cfg = heuristic_cfg(m, n);
-  if (splits <= 0) splits = heuristic_splits(m, make_plan(m, n, cfg, 1), di.cus);
+  if (splits <= 0) splits = heuristic_splits(m, make_plan(m, n, cfg, 1), di.cus, fp4 ? 2.0 : 1.0);
   *out = make_plan(m, n, cfg, splits);
+  // FP4 units accumulate in FP32: at most 2^24 rows each (more splits if needed).
+  while (fp4 && out->kchunk > kFp4MaxUnitRows) *out = make_plan(m, n, cfg, out->splits + 1);
   return MI_OK;
+}
+
+// The FP4 Gram for byte input when the library chooses: the conversion pass
+// (read the input, write half of it) costs about m n 1.5 B at HBM speed, and
+// the Gram saves about 40% of m n (n + 1) / 2 pair-updates at ~1.5e15 per
+// second; the saving exceeds the pass from about 1,500 columns on.  With few
+// rows the FP4 Gram still wins (half the 64-row steps, each with a fixed
+// cost: 0.160 against 0.177 ms at 2,000 x 8,192, conversion included).
+bool fp4_preferred(int64_t m, int64_t n) { return n >= 1536 && m >= 1024; }
+
+// Byte input converted to the FP4 layout first (requested, or the library's choice).
+bool converts_to_fp4(const mi_problem* p) {
+  return p->packed == MI_INPUT_BYTES && (p->gram == MI_GRAM_FP4 || (p->gram == MI_GRAM_AUTO && fp4_preferred(p->m, p->n)));
 }
 
 // -------------------------------------------------------------- arguments --
 // Rows of one 64-row stage are addressed with 32-bit offsets.
 static constexpr int64_t kMaxPitch = (int64_t)1 << 24;
 static constexpr int64_t kMaxCols = (int64_t)32767 * 128;
-mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
+mi_status check_problem(const mi_problem* p, int64_t* ldx_out, bool need_output) {
   if (!p) return fail(MI_ERR_INVALID_ARG, "problem is NULL");
   if (p->m <= 0) return fail(MI_ERR_INVALID_ARG, "m must be >= 1 (got %lld)", (long long)p->m);
   if (p->m > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "m must be <= 2^31-1 (int32 counts), got %lld", (long long)p->m);
@@ -281,11 +299,25 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
   const int64_t rb = row_bytes(*p);
   const int64_t ldx = p->ldx == 0 ? rb : p->ldx;
   if (ldx < rb) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < %lld bytes of a row", (long long)ldx, (long long)rb);
+  if (p->packed < MI_INPUT_BYTES || p->packed > MI_INPUT_FP4)
+    return fail(MI_ERR_INVALID_ARG, "bad input layout (packed = %d)", p->packed);
+  if (p->gram < MI_GRAM_AUTO || p->gram > MI_GRAM_FP4) return fail(MI_ERR_INVALID_ARG, "bad gram %d", p->gram);
+  if (p->packed == MI_INPUT_BITS && p->gram == MI_GRAM_FP4)
+    return fail(MI_ERR_INVALID_ARG, "bit-packed input takes the int8 Gram");
+  if (p->packed == MI_INPUT_FP4 && p->gram == MI_GRAM_INT8)
+    return fail(MI_ERR_INVALID_ARG, "FP4 input takes the FP4 Gram");
+  if (p->packed == MI_INPUT_FP4 && p->validate)
+    return fail(MI_ERR_INVALID_ARG, "validate is not available for FP4 input (validate the bytes before packing)");
   if (p->packed && p->algo != MI_ALGO_DENSE)
     return fail(MI_ERR_INVALID_ARG, "packed input takes only the dense algorithm");
+  if (p->gram == MI_GRAM_FP4 && p->algo == MI_ALGO_SPARSE)
+    return fail(MI_ERR_INVALID_ARG, "the FP4 Gram is a dense-algorithm choice");
   if (ldx > kMaxPitch) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) above the supported 2^24", (long long)ldx);
+  // 128-row FP4 stages are addressed with 32-bit offsets.
+  if (p->packed == MI_INPUT_FP4 && ldx > kMaxPitch / 2)
+    return fail(MI_ERR_INVALID_ARG, "ldx (%lld) above the supported 2^23 for FP4 input", (long long)ldx);
   if (p->n > 0 && !p->X) return fail(MI_ERR_INVALID_ARG, "X must be non-NULL when n > 0");
-  if (p->n > 0 && !p->out && !p->pairs && !p->n11_out)
+  if (need_output && p->n > 0 && !p->out && !p->pairs && !p->n11_out)
     return fail(MI_ERR_INVALID_ARG, "out, n11_out or the sparse pairs output must be given when n > 0");
   if (p->algo < MI_ALGO_DENSE || p->algo > MI_ALGO_AUTO) return fail(MI_ERR_INVALID_ARG, "bad algo %d", p->algo);
   if (p->pairs && (!p->pairs_count || p->pairs_capacity < 0 || !std::isfinite(p->pairs_threshold)))
@@ -300,8 +332,11 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out) {
 
 bool is_aligned(const uint8_t* X, int64_t ldx) { return ((uintptr_t)X % 16 == 0) && (ldx % 16 == 0); }
 
-// Bytes of a row that hold columns: n, or ceil(n / 8) for bit-packed input.
-int64_t row_bytes(const mi_problem& p) { return p.packed ? (p.n + 7) / 8 : p.n; }
+// Bytes of a row that hold columns: n, ceil(n / 8) for bit-packed input,
+// ceil(n / 2) for FP4 input.
+int64_t row_bytes(const mi_problem& p) {
+  return p.packed == MI_INPUT_BITS ? (p.n + 7) / 8 : (p.packed == MI_INPUT_FP4 ? (p.n + 1) / 2 : p.n);
+}
 
 ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const Plan& pl, void* ws,
                      const int32_t* tiles) {
@@ -324,7 +359,7 @@ ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const P
   P.ksteps = (int32_t)pl.ksteps;
   P.kchunk = pl.kchunk;
   P.epi = (!p->out && !p->pairs) ? kEpiCounts : p->epilogue;  // counts alone: no MI evaluated
-  P.packed = p->packed ? 1 : 0;
+  P.packed = p->packed;
   P.tau = p->fallback_tau > 0.0f ? p->fallback_tau : 1e-3f;
   P.splits = pl.splits;
   P.tiles_per_xcd = pl.tpx;
@@ -374,12 +409,23 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_o
     if (s != MI_OK || used) return s;
   }
   const bool aligned = is_aligned(p->X, ldx);
+  const bool convert = converts_to_fp4(p);
+  const bool fp4 = convert || p->packed == MI_INPUT_FP4;
   Plan pl;
-  s = choose_plan(p->m, p->n, aligned, p->tile, p->splits, &pl);
+  s = choose_plan(p->m, p->n, aligned || convert, p->tile, p->splits, &pl, fp4);
   if (s != MI_OK) return s;
   const uint8_t* X = p->X;
   int64_t ld = ldx;
-  if (!aligned) {
+  mi_problem q = *p;  // the problem as the kernel sees it
+  if (convert) {
+    q.packed = MI_INPUT_FP4;
+    ld = packed_pitch(row_bytes(q));
+    void* buf = nullptr;
+    s = scratch(st, 7, ws_slot, (size_t)p->m * (size_t)ld, &buf);
+    if (s != MI_OK) return s;
+    HIPCHK(launch_pack_fp4(p->X, p->m, p->n, ldx, (uint8_t*)buf, ld, st));
+    X = (const uint8_t*)buf;
+  } else if (!aligned) {
     ld = packed_pitch(row_bytes(*p));
     void* buf = nullptr;
     s = scratch(st, 1, ws_slot, (size_t)p->m * (size_t)ld, &buf);
@@ -393,7 +439,7 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_o
   hipError_t e;
   const int32_t* tiles = tile_table(pl.ntp, &e);
   if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(e));
-  ProbDev P = make_probdev(p, X, ld, pl, ws, tiles);
+  ProbDev P = make_probdev(&q, X, ld, pl, ws, tiles);
   P.upper_only = upper_only ? 1 : 0;
   HIPCHK(launch_plain(pl.cfg, P, st));
   return MI_OK;
@@ -456,6 +502,9 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
       return fail(MI_ERR_INVALID_ARG, "problem %lld: batches take only the dense algorithm", (long long)d);
     if (probs[d].packed && mode == MI_BATCH_PERSISTENT)
       return fail(MI_ERR_INVALID_ARG, "problem %lld: the persistent mode takes only the byte layout", (long long)d);
+    if (probs[d].gram == MI_GRAM_FP4 && probs[d].packed != MI_INPUT_FP4)
+      return fail(MI_ERR_INVALID_ARG,
+                  "problem %lld: batches run the FP4 Gram on FP4 input only (pack it with mi_pack_fp4)", (long long)d);
   }
   DeviceInfo di;
   s = device_info(&di);
@@ -505,7 +554,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   } else {
     for (int64_t d = 0; d < count; ++d) {
       if (probs[d].n == 0) continue;
-      s = choose_plan(probs[d].m, probs[d].n, aligned[d], probs[d].tile, probs[d].splits, &plans[d]);
+      s = choose_plan(probs[d].m, probs[d].n, aligned[d], probs[d].tile, probs[d].splits, &plans[d],
+                      probs[d].packed == MI_INPUT_FP4);
       if (s != MI_OK) return s;
     }
   }
@@ -898,6 +948,35 @@ mi_status mi_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint
   if (ldp < (n + 7) / 8) return fail(MI_ERR_INVALID_ARG, "ldp (%lld) < ceil(n / 8)", (long long)ldp);
   if ((n + 63) / 64 > (int64_t)64 * 65535) return fail(MI_ERR_INVALID_ARG, "n too large");
   HIPCHK(launch_pack_bits(X, m, n, ldx, Xp, ldp, (hipStream_t)stream));
+  return MI_OK;
+}
+
+mi_status mi_pack_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xq, int64_t ldq, void* stream) {
+  clear_error();
+  if (m < 0 || n < 0) return fail(MI_ERR_INVALID_ARG, "m and n must be >= 0");
+  if (m == 0 || n == 0) return MI_OK;
+  if (!X || !Xq) return fail(MI_ERR_INVALID_ARG, "X and Xq must be non-NULL");
+  if (ldx < n) return fail(MI_ERR_INVALID_ARG, "ldx (%lld) < n (%lld)", (long long)ldx, (long long)n);
+  if (ldq < (n + 1) / 2) return fail(MI_ERR_INVALID_ARG, "ldq (%lld) < ceil(n / 2)", (long long)ldq);
+  if ((n + 31) / 32 > (int64_t)64 * 65535) return fail(MI_ERR_INVALID_ARG, "n too large");
+  if ((m + 3) / 4 > (int64_t)UINT32_MAX) return fail(MI_ERR_INVALID_ARG, "m too large");
+  HIPCHK(launch_pack_fp4(X, m, n, ldx, Xq, ldq, (hipStream_t)stream));
+  return MI_OK;
+}
+
+mi_status mi_plan_ex(const mi_problem* p, int32_t* tile, int32_t* splits, int32_t* gram) {
+  clear_error();
+  int64_t ldx = 0;
+  mi_status s = check_problem(p, &ldx, /*need_output=*/false);
+  if (s != MI_OK) return s;
+  const bool convert = converts_to_fp4(p);
+  const bool fp4 = convert || p->packed == MI_INPUT_FP4;
+  Plan pl;
+  s = choose_plan(p->m, std::max<int64_t>(p->n, 1), is_aligned(p->X, ldx) || convert, p->tile, p->splits, &pl, fp4);
+  if (s != MI_OK) return s;
+  if (tile) *tile = pl.cfg == 1 ? MI_TILE_256 : MI_TILE_128;
+  if (splits) *splits = pl.splits;
+  if (gram) *gram = fp4 ? MI_GRAM_FP4 : MI_GRAM_INT8;
   return MI_OK;
 }
 

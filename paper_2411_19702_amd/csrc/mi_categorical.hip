@@ -64,6 +64,9 @@ __device__ __forceinline__ uint32_t eq_bytes(uint32_t a, uint32_t b) {
 //    adjacent window dwords with one byte permute, and compares all 4 codes
 //    at once.  Chunks whose variables do not fit that window (single-level
 //    variables leave gaps) and unaligned layouts load byte by byte.
+//    F4: Y holds the FP4 layout of the indicators instead (two columns per
+//    byte, a one as the E2M1 code of 1.0), 8 bytes per chunk, for the FP4 Gram.
+template <bool F4>
 __global__ __launch_bounds__(256) void k_cat_expand(const uint8_t* __restrict__ X, int64_t ldx, int64_t m,
                                                     const int32_t* __restrict__ colmap, int32_t cpr, int32_t cg,
                                                     int64_t rows_per_block, int32_t aligned,
@@ -132,7 +135,16 @@ __global__ __launch_bounds__(256) void k_cat_expand(const uint8_t* __restrict__ 
         o[q] = indicator(xr, ent[4 * q]) | (indicator(xr, ent[4 * q + 1]) << 8) |
                (indicator(xr, ent[4 * q + 2]) << 16) | (indicator(xr, ent[4 * q + 3]) << 24);
     }
-    *reinterpret_cast<uint4*>(Y + r * ldy + (int64_t)ch * 16) = make_uint4(o[0], o[1], o[2], o[3]);
+    if constexpr (F4) {
+      // Bytes 0/1 of a dword to the 0b0010 codes of four nibbles (16 bits).
+      auto nib = [](uint32_t d) {
+        return ((d & 1u) << 1) | ((d >> 3) & 0x20u) | ((d >> 7) & 0x200u) | ((d >> 11) & 0x2000u);
+      };
+      *reinterpret_cast<uint2*>(Y + r * ldy + (int64_t)ch * 8) =
+          make_uint2(nib(o[0]) | (nib(o[1]) << 16), nib(o[2]) | (nib(o[3]) << 16));
+    } else {
+      *reinterpret_cast<uint4*>(Y + r * ldy + (int64_t)ch * 16) = make_uint4(o[0], o[1], o[2], o[3]);
+    }
   }
 }
 
@@ -327,6 +339,7 @@ mi_status check_cat(const mi_cat_problem* p, int64_t* ldx_out, int64_t* N_out) {
   if (p->epilogue < 0 || p->epilogue > 2) return fail(MI_ERR_INVALID_ARG, "bad epilogue mode %d", p->epilogue);
   if (p->tile < 0 || p->tile > 2) return fail(MI_ERR_INVALID_ARG, "bad tile id %d", p->tile);
   if (p->splits < 0) return fail(MI_ERR_INVALID_ARG, "splits must be >= 0");
+  if (p->gram < MI_GRAM_AUTO || p->gram > MI_GRAM_FP4) return fail(MI_ERR_INVALID_ARG, "bad gram %d", p->gram);
   int64_t N = 0;
   if (p->pairs && (!p->pairs_count || p->pairs_capacity < 0 || !std::isfinite(p->pairs_threshold)))
     return fail(MI_ERR_INVALID_ARG, "pairs needs pairs_count, pairs_capacity >= 0 and a finite threshold");
@@ -410,8 +423,12 @@ mi_status run_categorical(const mi_cat_problem* p, hipStream_t st) {
   int32_t* sums = p->sums_out ? p->sums_out : d_sums;
   const int32_t* G = nullptr;
   if (N > 0) {
+    // The indicators go straight to the FP4 layout (half the bytes, no
+    // conversion pass) when the FP4 Gram runs.
+    const bool f4 = p->gram == MI_GRAM_FP4 || (p->gram == MI_GRAM_AUTO && fp4_preferred(m, N));
+    const int64_t ldyg = f4 ? packed_pitch((N + 1) / 2) : ldy;  // pitch of the Gram's input
     void* ybuf = nullptr;
-    s = scratch(st, 4, 0, (size_t)m * (size_t)ldy, &ybuf);
+    s = scratch(st, 4, 0, (size_t)m * (size_t)ldyg, &ybuf);
     if (s != MI_OK) return s;
     uint8_t* Y = (uint8_t*)ybuf;
     const int32_t cpr = (int32_t)(ldy / 16);
@@ -420,8 +437,12 @@ mi_status run_categorical(const mi_cat_problem* p, hipStream_t st) {
     const int64_t rows_per_block = 256;
     const dim3 eg((unsigned)cdiv(m, rows_per_block), (unsigned)cdiv(cpr, cg));
     const int32_t aligned = ((uintptr_t)p->X % 16 == 0 && ldx % 16 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(k_cat_expand, eg, dim3(256), 0, st, p->X, ldx, m, d_map, cpr, cg, rows_per_block, aligned, Y,
-                       ldy);
+    if (f4)
+      hipLaunchKernelGGL(k_cat_expand<true>, eg, dim3(256), 0, st, p->X, ldx, m, d_map, cpr, cg, rows_per_block,
+                         aligned, Y, ldyg);
+    else
+      hipLaunchKernelGGL(k_cat_expand<false>, eg, dim3(256), 0, st, p->X, ldx, m, d_map, cpr, cg, rows_per_block,
+                         aligned, Y, ldyg);
     HIPCHK(hipGetLastError());
     int32_t* Gw = p->counts_out;
     if (!Gw) {
@@ -432,7 +453,8 @@ mi_status run_categorical(const mi_cat_problem* p, hipStream_t st) {
     }
     mi_problem q;
     mi_problem_init(&q, Y, m, N, nullptr);
-    q.ldx = ldy;
+    q.ldx = ldyg;
+    q.packed = f4 ? MI_INPUT_FP4 : MI_INPUT_BYTES;
     q.n11_out = Gw;
     q.colsum_out = sums;
     q.tile = p->tile;

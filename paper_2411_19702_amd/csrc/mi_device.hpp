@@ -40,9 +40,18 @@ typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 #define MI_LDS __attribute__((address_space(3)))
 
 constexpr int KT = 64;  // samples per stage = one MFMA K step
+// Input layouts of the plain kernel: 0/1 bytes, 8 columns per byte (bits),
+// or 2 columns per byte as E2M1 (FP4) codes for the FP4 matrix path.
+constexpr int kInBytes = 0, kInBits = 1, kInFp4 = 2;
+constexpr int KT4 = 128;  // samples per stage of the FP4 layout: two K steps of 64
+// An FP4 unit accumulates in FP32, exact for counts up to 2^24: at most this
+// many rows per unit.
+constexpr int64_t kFp4MaxUnitRows = (int64_t)1 << 24;
 
 // Tile configuration: BT x BT output tile, WGM x WGN waves, NS-stage LDS ring.
 template <int BT_, int WGM_, int WGN_, int NS_>
@@ -58,10 +67,14 @@ struct Cfg {
   static constexpr int LOADS = REGIONS / NWAVES;        // DMA instructions per wave per stage
   static constexpr int ROWS_PER_REGION = 1024 / BT;
   static constexpr int SEGS = BT / 16;                  // 16-byte segments per row
+  static constexpr int RB4 = BT / 2;                    // FP4 layout: bytes of one panel row
+  static constexpr int ROWS_PER_REGION4 = 1024 / RB4;
+  static constexpr int SEGS4 = RB4 / 16;
   static constexpr int STRIP = 32 * WTN;                // epilogue strip elements per wave
   static constexpr int STRIP_BYTES = 2 * STRIP * 4;     // int32 counts + FP32 MI of a strip
   static constexpr int WAVES_PER_SLOT = STAGE / STRIP_BYTES;
   static_assert(NS == 4, "the K loop is unrolled over four ring slots");
+  static_assert(KT4 * RB4 == PANEL, "an FP4 stage holds as many bytes as a byte stage");
   static_assert(REGIONS % NWAVES == 0, "DMA regions must split evenly over waves");
   static_assert(WAVES_PER_SLOT >= 1 && NWAVES <= NS * WAVES_PER_SLOT, "epilogue strips must fit in the ring");
 };
@@ -91,7 +104,8 @@ struct ProbDev {
   int32_t tiles_per_xcd;  // plain launch: tiles owned by each of the 8 XCDs
   int32_t epi;          // mi_epilogue, or kEpiCounts: counts only, no MI evaluated
   int32_t upper_only;   // nonzero: store i <= j only (no mirror writes)
-  int32_t packed;       // X holds 8 columns per byte (bit k of byte b = column 8 b + k); ldx in bytes
+  int32_t packed;       // kInBytes; kInBits: bit k of byte b = column 8 b + k; kInFp4: two E2M1
+                        // codes per byte (column 2 b in the low nibble); ldx in bytes
   float tau;
   // Sparse output: pairs i < j with MI >= thr, appended at an atomic counter
   // (stored while the count stays below cap).  pairs == nullptr: none.
@@ -202,14 +216,62 @@ __device__ __forceinline__ v4i read_frag(const uint8_t* p) {
   return v4i{lo.x, lo.y, hi.x, hi.y};
 }
 
+// ---------------------------------------------------------------------------
+// FP4 layout: two columns per byte (column 2 c in the low nibble of byte c), a
+// one stored as the E2M1 code of 1.0 and a zero as 0.  The exact 0/1 products
+// then sum to the integer counts in the FP32 accumulator (exact below 2^24).
+// A stage is 128 sample rows of BT / 2 bytes per panel: the same bytes as 64
+// rows of the byte layout, for twice the samples.
+//
+// Operands of v_mfma_scale_f32_32x32x64_f8f6f4 with E2M1 operands and unit
+// scales: lane l holds 32 samples (k = (l / 32) * 32 ..) of fragment column
+// l % 32, one per nibble, in four registers (the upper four of the 8-register
+// operand are not read for E2M1).  They are read with ds_read_b64_tr_b4, a
+// nibble transpose within each group of 16 lanes: source lane q addresses 8
+// bytes (16 columns) of one sample row, and output lane i receives column i of
+// the 16 rows, in source-lane order.  Lane group G = l / 16 therefore reads the
+// column half G & 1 (8 bytes of the fragment's 16-byte segment) at sample rows
+// (G / 2) * 32 + 0..15, and + 16 for its other 16 samples.
+//
+// A half-wave reads 16 consecutive rows at one segment; g spreads them over 16
+// distinct 4-bank groups:
+//   BT = 256 (a row is 128 bytes, two rows span the 64 banks): g = (r >> 1) & 7;
+//   BT = 128 (a row is 64 bytes, four rows span the banks):     g = (r >> 2) & 3.
+// g(r + 16) = g(r), so the second read (rows + 16) and the second K step of a
+// stage (rows + 64) are at fixed offsets from the first read.
+// ---------------------------------------------------------------------------
+template <int BT>
+__device__ __forceinline__ int seg_swz4(int row) {
+  if (BT == 256) return (row >> 1) & 7;
+  return (row >> 2) & 3;
+}
+
+// Byte offset (inside one panel) of this lane's first transposed read for the
+// 32-column fragment in segment s (columns 32 s ..).
+template <int BT>
+__device__ __forceinline__ int frag_off4(int s, int lane) {
+  const int G = lane >> 4, q = lane & 15;
+  const int row = (G >> 1) * 32 + q;
+  return row * (BT / 2) + ((s ^ seg_swz4<BT>(row)) << 4) + ((G & 1) << 3);
+}
+
+// One FP4 operand fragment (32 columns x 32 samples per lane, one 64-sample K
+// step): two transposed 16-sample reads, 16 rows apart.
+template <int BT>
+__device__ __forceinline__ v4i read_frag4(const uint8_t* p) {
+  const v2i lo = __builtin_amdgcn_ds_read_tr4_b64_v2i32((MI_LDS v2i*)(p));
+  const v2i hi = __builtin_amdgcn_ds_read_tr4_b64_v2i32((MI_LDS v2i*)(p + 16 * (BT / 2)));
+  return v4i{lo.x, lo.y, hi.x, hi.y};
+}
+
 __device__ __forceinline__ uint32_t sgpr(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Buffer descriptor for one stage: `rem` rows of X are left from `base` on
 // (rem <= 0 past the end of the unit); reads at byte offsets past
-// min(rem, KT) rows return zeros and touch no memory.  All arguments are
+// min(rem, kt) rows return zeros and touch no memory.  All arguments are
 // workgroup-uniform scalars.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t stage_rsrc(uint64_t base, int rem, int ldx) {
-  const int rows = rem >= KT ? KT : max(rem, 0);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stage_rsrc(uint64_t base, int rem, int ldx, int kt = KT) {
+  const int rows = rem >= kt ? kt : max(rem, 0);
   const uint32_t lo = sgpr((uint32_t)base), hi = sgpr((uint32_t)(base >> 32));
   const int nrec = (int)sgpr((uint32_t)(rows * ldx));
   return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), 0, nrec, 0x00020000);
@@ -242,13 +304,18 @@ __device__ __forceinline__ uint4 unpack16(uint32_t w) {
                     (((w >> 8) & 0xFu) * k) & 0x01010101u, (((w >> 12) & 0xFu) * k) & 0x01010101u);
 }
 
-// One work unit.  PK: X is bit-packed; each stage is loaded into registers
+// One work unit.  IN: the input layout (kInBytes, kInBits, kInFp4).  With
+// kInFp4 the stages are 128 rows of FP4 codes and the Gram runs on the FP4
+// matrix instructions (FP32 accumulators, converted to the int32 counts after
+// the K loop).  With kInBits X is bit-packed; each stage is loaded into registers
 // (one 8-byte load per thread, four stages ahead), unpacked to bytes and
 // written to the ring, instead of the buffer-to-LDS DMA of the byte layout.
-template <class C, bool PK = false>
+template <class C, int IN = kInBytes>
 __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1, const Smem<C>& sm) {
 #if defined(__HIP_DEVICE_COMPILE__)  // device-only body (gfx950 builtins and asm)
   constexpr int BT = C::BT, FM = C::FM, FN = C::FN;
+  constexpr bool PK = IN == kInBits, F4 = IN == kInFp4;
+  constexpr int KS = F4 ? KT4 : KT;  // sample rows per stage
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = (int)sgpr((uint32_t)(tid >> 6));  // wave-uniform: scalar branches on it
@@ -271,7 +338,19 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   // physical segment l % SEGS, which holds logical segment (l % SEGS) ^ f(row).
   int voff[C::LOADS];
   uint32_t ldsoff[C::LOADS];
-  if constexpr (!PK) {
+  if constexpr (F4) {
+    // The same regions over 128 rows of BT / 2 bytes (ROWS_PER_REGION4 rows each).
+#pragma unroll
+    for (int i = 0; i < C::LOADS; ++i) {
+      const int R = i * C::NWAVES + wave;
+      const int panel = R / (C::REGIONS / 2);
+      const int row = (R % (C::REGIONS / 2)) * C::ROWS_PER_REGION4 + lane / C::SEGS4;
+      const int seg = (lane % C::SEGS4) ^ seg_swz4<BT>(row);
+      const int col0 = (panel == 0 ? I : J) * C::RB4;
+      voff[i] = row * (int)P.ldx + col0 + 16 * seg;
+      ldsoff[i] = (uint32_t)R * 1024u;
+    }
+  } else if constexpr (!PK) {
 #pragma unroll
     for (int i = 0; i < C::LOADS; ++i) {
       const int R = i * C::NWAVES + wave;
@@ -296,13 +375,13 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     for (int g = 0; g < 4; ++g)
       pwoff[g] = (uint32_t)(panel * C::PANEL + row * BT + (((4 * q + g) ^ seg_swz<BT>(row)) << 4));
   }
-  // Stage j of the unit starts at row k0 + j KT; its base address advances by
-  // KT * ldx bytes per stage (scalar adds, no per-stage multiplies).
+  // Stage j of the unit starts at row k0 + j KS; its base address advances by
+  // KS * ldx bytes per stage (scalar adds, no per-stage multiplies).
   const int ldx32 = (int)P.ldx;
-  const uint64_t stage_bytes = (uint64_t)KT * (uint64_t)P.ldx;
+  const uint64_t stage_bytes = (uint64_t)KS * (uint64_t)P.ldx;
   const uint64_t xk0 = (uint64_t)(P.X + (int64_t)k0 * P.ldx);
   auto dma_stage = [&](uint64_t base, int rem, uint8_t* slot) {
-    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(base, rem, ldx32);
+    const __amdgpu_buffer_rsrc_t rs = stage_rsrc(base, rem, ldx32, KS);
 #pragma unroll
     for (int i = 0; i < C::LOADS; ++i)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (MI_LDS void*)(slot + ldsoff[i]), 16, voff[i], 0, 0, 0);
@@ -324,10 +403,17 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
 
   // Operand read offsets (inside a stage) for this lane's fragments.
   uint32_t aoff[FM], boff[FN];
+  if constexpr (F4) {
 #pragma unroll
-  for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off<BT>((wm * C::WTM) / 16 + 2 * blk_a(a), lane);
+    for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off4<BT>((wm * C::WTM) / 32 + blk_a(a), lane);
 #pragma unroll
-  for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off<BT>((wn * C::WTN) / 16 + 2 * blk_b(b), lane));
+    for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off4<BT>((wn * C::WTN) / 32 + blk_b(b), lane));
+  } else {
+#pragma unroll
+    for (int a = 0; a < FM; ++a) aoff[a] = (uint32_t)frag_off<BT>((wm * C::WTM) / 16 + 2 * blk_a(a), lane);
+#pragma unroll
+    for (int b = 0; b < FN; ++b) boff[b] = (uint32_t)(C::PANEL + frag_off<BT>((wn * C::WTN) / 16 + 2 * blk_b(b), lane));
+  }
 
   v16i acc[FM][FN];
 #pragma unroll
@@ -351,12 +437,21 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   // the barrier that publishes the next stage sits between the two halves,
   // so matrix work is queued while the wave waits at it.
   v4i fa0[FM], fb0[FN], fa1[FM], fb1[FN];
+  // Half kk of a stage starts at byte kk * 32 * BT of each panel in both
+  // layouts (32 byte rows, or 64 FP4 rows of BT / 2 bytes).
   auto read_half = [&](const uint8_t* slot, int kk, v4i (&fa)[FM], v4i (&fb)[FN]) {
     const uint8_t* kb = slot + kk * 32 * BT;
+    if constexpr (F4) {
 #pragma unroll
-    for (int b = 0; b < FN; ++b) fb[b] = read_frag<BT>(kb + boff[b]);
+      for (int b = 0; b < FN; ++b) fb[b] = read_frag4<BT>(kb + boff[b]);
 #pragma unroll
-    for (int a = 0; a < FM; ++a) fa[a] = read_frag<BT>(kb + aoff[a]);
+      for (int a = 0; a < FM; ++a) fa[a] = read_frag4<BT>(kb + aoff[a]);
+    } else {
+#pragma unroll
+      for (int b = 0; b < FN; ++b) fb[b] = read_frag<BT>(kb + boff[b]);
+#pragma unroll
+      for (int a = 0; a < FM; ++a) fa[a] = read_frag<BT>(kb + aoff[a]);
+    }
   };
   auto mma_half = [&](const v4i (&fa)[FM], const v4i (&fb)[FN]) {
 #pragma unroll
@@ -452,6 +547,70 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
         pkB[y] = 0u;
       }
     }
+  } else if constexpr (F4) {
+    // The byte loop's schedule over 128-row FP4 stages; each half is one
+    // 64-sample K step of the FP4 instruction.  Column sums: a one is the
+    // code 0b0010, so a fragment's popcount is its count of ones.
+    v16f accf[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) accf[a][b][r] = 0.0f;
+    auto mma_half4 = [&](const v4i (&fa)[FM], const v4i (&fb)[FN]) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          accf[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              v8i{fa[a].x, fa[a].y, fa[a].z, fa[a].w, 0, 0, 0, 0}, v8i{fb[b].x, fb[b].y, fb[b].z, fb[b].w, 0, 0, 0, 0},
+              accf[a][b], 4, 4, 0, 127, 0, 127);  // E2M1 x E2M1, scales 2^0
+#pragma unroll
+      for (int x = 0; x < SA; ++x)
+        csA[x] += (__builtin_popcount((uint32_t)fa[x].x) + __builtin_popcount((uint32_t)fa[x].y)) +
+                  (__builtin_popcount((uint32_t)fa[x].z) + __builtin_popcount((uint32_t)fa[x].w));
+#pragma unroll
+      for (int y = 0; y < SB; ++y)
+        csB[y] += (__builtin_popcount((uint32_t)fb[y].x) + __builtin_popcount((uint32_t)fb[y].y)) +
+                  (__builtin_popcount((uint32_t)fb[y].z) + __builtin_popcount((uint32_t)fb[y].w));
+    };
+    dma_stage(xk0, rows, sm.slot[0]);
+    dma_stage(xk0 + stage_bytes, rows - KS, sm.slot[1]);
+    dma_stage(xk0 + 2 * stage_bytes, rows - 2 * KS, sm.slot[2]);
+    stage_barrier();
+    dma_stage(xk0 + 3 * stage_bytes, rows - 3 * KS, sm.slot[3]);
+    read_half(sm.slot[0], 0, fa0, fb0);
+    uint64_t dbase = xk0 + 4 * stage_bytes;
+    int drem = rows - 4 * KS;
+    auto do_step4 = [&](uint8_t* cur, uint8_t* nxt) {
+      read_half(cur, 1, fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_half4(fa0, fb0);
+      __builtin_amdgcn_sched_barrier(0);
+      stage_barrier();
+      dma_stage(dbase, drem, cur);
+      dbase += stage_bytes;
+      drem -= KS;
+      read_half(nxt, 0, fa0, fb0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_half4(fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    const int nstages = (rows + KS - 1) / KS;
+    for (int step = 0; step < nstages; step += 4) {
+      do_step4(sm.slot[0], sm.slot[1]);
+      do_step4(sm.slot[1], sm.slot[2]);
+      do_step4(sm.slot[2], sm.slot[3]);
+      do_step4(sm.slot[3], sm.slot[0]);
+    }
+    // Counts of at most 2^24 rows are exact in FP32.
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[a][b][r] = (int)accf[a][b][r];
   } else {
   // Prologue: stages 0 .. 2 in flight in slots 0 .. 2; once stage 0 is in,
   // stage 3 goes to slot 3 and the first half of stage 0 is read.

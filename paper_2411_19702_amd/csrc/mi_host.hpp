@@ -42,8 +42,15 @@ mi_status workspace(hipStream_t st, int slot, size_t bytes, void** out);  // zer
 size_t workspace_bytes(const Plan& pl);
 Plan make_plan(int64_t m, int64_t n, int cfg, int splits);
 const int32_t* tile_table(int ntp, hipError_t* err);
-mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out);
-mi_status check_problem(const mi_problem* p, int64_t* ldx_out);
+// fp4: the plan of the FP4 Gram (heuristic only, at most 2^24 rows per unit).
+mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int splits_req, Plan* out,
+                      bool fp4 = false);
+// The library's choice of the FP4 Gram for an m x n 0/1 problem.
+bool fp4_preferred(int64_t m, int64_t n);
+// Byte input that the dense path converts to FP4 first (requested, or the library's choice).
+bool converts_to_fp4(const mi_problem* p);
+// need_output: n > 0 needs out, n11_out or pairs (not for planning queries).
+mi_status check_problem(const mi_problem* p, int64_t* ldx_out, bool need_output = true);
 bool is_aligned(const uint8_t* X, int64_t ldx);
 int64_t row_bytes(const mi_problem& p);
 ProbDev make_probdev(const mi_problem* p, const uint8_t* X, int64_t ldx, const Plan& pl, void* ws,

@@ -42,6 +42,8 @@ hipError_t launch_repack_batch(const RepackDesc* descs, int count, int64_t block
 int64_t repack_blocks(int64_t m, int64_t ldy);
 hipError_t launch_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xp, int64_t ldp,
                             hipStream_t st);
+hipError_t launch_pack_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xq, int64_t ldq,
+                           hipStream_t st);
 hipError_t fill_i32(int* p, int v, int count, hipStream_t st);
 int occupancy(int cfg);
 int persistent_occupancy(int cfg);

@@ -22,7 +22,7 @@ namespace mi {
 // spread over XCDs, or each workgroup streaming its own share of all tiles)
 // measured 1.2-1.7x slower on the 1,000,000 x 4,096 workload, whose input
 // does not fit the last-level cache.  Padding units of the grid exit at once.
-template <class C, bool PK>
+template <class C, int IN>
 __global__ __launch_bounds__(C::NT) void k_plain(ProbDev P) {
   MI_DECLARE_SMEM(C, sm);
   const int u = blockIdx.x;
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(C::NT) void k_plain(ProbDev P) {
   const int t = xcd * tpx + (local - s * tpx);
   if (t >= P.ntiles || s >= P.splits) return;  // uniform
   const int k0 = s * P.kchunk;
-  run_unit<C, PK>(P, t, k0, min(P.m, k0 + P.kchunk), sm);
+  run_unit<C, IN>(P, t, k0, min(P.m, k0 + P.kchunk), sm);
 }
 
 // Persistent workgroups pull units of many datasets from a device queue.
@@ -185,13 +185,72 @@ hipError_t launch_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx,
   return hipGetLastError();
 }
 
+// Byte -> FP4 packing (the layout of the FP4 path): two columns per byte,
+// column 2 c in the low nibble of byte c, the E2M1 code of 1.0 (0b0010) for a
+// nonzero byte and 0 for a zero.  Four input bytes give 16 output bits: bit 7
+// of each nonzero byte (the carry-free test of nibble_of) moves to bit 1 of
+// its nibble.
+__device__ __forceinline__ uint32_t fp4_of(uint32_t d) {
+  const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
+  return ((nz >> 6) & 0x2u) | ((nz >> 10) & 0x20u) | ((nz >> 14) & 0x200u) | ((nz >> 18) & 0x2000u);
+}
+
+// One thread per (row, 32-column group): 16 packed bytes.  Blocks cover 4
+// rows x 64 groups.  Groups that end past n, and unaligned layouts, go byte by
+// byte; bytes of the destination past ceil(n / 2) are not written.
+__global__ __launch_bounds__(256) void k_pack_fp4(const uint8_t* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                                                  uint8_t* __restrict__ Xq, int64_t ldq, int32_t vec_in,
+                                                  int32_t vec_out) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int64_t g = (int64_t)blockIdx.y * 64 + threadIdx.x % 64;
+  const int64_t nbytes = (n + 1) / 2;  // packed bytes of a row that hold columns
+  if (r >= m || 16 * g >= nbytes) return;
+  const uint8_t* xr = X + r * ldx + 32 * g;
+  uint8_t* qr = Xq + r * ldq + 16 * g;
+  if (vec_in && 32 * g + 32 <= n) {
+    const uint4 a = *reinterpret_cast<const uint4*>(xr);
+    const uint4 b = *reinterpret_cast<const uint4*>(xr + 16);
+    const uint4 o = make_uint4(fp4_of(a.x) | (fp4_of(a.y) << 16), fp4_of(a.z) | (fp4_of(a.w) << 16),
+                               fp4_of(b.x) | (fp4_of(b.y) << 16), fp4_of(b.z) | (fp4_of(b.w) << 16));
+    if (vec_out) {
+      *reinterpret_cast<uint4*>(qr) = o;
+    } else {
+      const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) qr[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
+    }
+    return;
+  }
+  const int64_t bytes = nbytes - 16 * g < 16 ? nbytes - 16 * g : 16;
+  for (int64_t k = 0; k < bytes; ++k) {
+    const int64_t c = 32 * g + 2 * k;  // columns c and c + 1 of this byte
+    uint32_t v = 0;
+    if (c < n && xr[2 * k] != 0) v |= 0x02u;
+    if (c + 1 < n && xr[2 * k + 1] != 0) v |= 0x20u;
+    qr[k] = (uint8_t)v;
+  }
+}
+
+hipError_t launch_pack_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xq, int64_t ldq,
+                           hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t groups = (n + 31) / 32;
+  const int32_t vec_in = ((uintptr_t)X % 16 == 0 && ldx % 16 == 0) ? 1 : 0;
+  const int32_t vec_out = ((uintptr_t)Xq % 16 == 0 && ldq % 16 == 0) ? 1 : 0;
+  const dim3 grid((unsigned)((m + 3) / 4), (unsigned)((groups + 63) / 64));
+  hipLaunchKernelGGL(k_pack_fp4, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, vec_in, vec_out);
+  return hipGetLastError();
+}
+
 template <class C>
 static hipError_t launch_plain_c(const ProbDev& P, hipStream_t st) {
   const int64_t grid = 8LL * P.tiles_per_xcd * P.splits;
-  if (P.packed)
-    hipLaunchKernelGGL((k_plain<C, true>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
+  if (P.packed == kInFp4)
+    hipLaunchKernelGGL((k_plain<C, kInFp4>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
+  else if (P.packed == kInBits)
+    hipLaunchKernelGGL((k_plain<C, kInBits>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
   else
-    hipLaunchKernelGGL((k_plain<C, false>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
+    hipLaunchKernelGGL((k_plain<C, kInBytes>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
   return hipGetLastError();
 }
 
@@ -250,8 +309,8 @@ int cfg_threads(int cfg) { return cfg == 1 ? Cfg256::NT : Cfg128::NT; }
 
 int occupancy(int cfg) {
   int blocks = 0;
-  hipError_t e = cfg == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg256, false>, Cfg256::NT, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg128, false>, Cfg128::NT, 0);
+  hipError_t e = cfg == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg256, kInBytes>, Cfg256::NT, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_plain<Cfg128, kInBytes>, Cfg128::NT, 0);
   if (e != hipSuccess || blocks < 1) blocks = 1;
   return blocks;
 }

@@ -337,8 +337,10 @@ mi_status mi_server_submit(mi_server* s, const mi_problem* p, uint64_t* ticket) 
   if (p->validate) return mi::fail(MI_ERR_INVALID_ARG, "validate is not supported by the server");
   if (p->algo != MI_ALGO_DENSE) return mi::fail(MI_ERR_INVALID_ARG, "the server takes only the dense algorithm");
   if (p->packed) return mi::fail(MI_ERR_INVALID_ARG, "the server takes only the byte layout");
+  if (p->gram == MI_GRAM_FP4) return mi::fail(MI_ERR_INVALID_ARG, "the server runs the int8 Gram");
   Req r;
   r.p = *p;
+  r.p.gram = MI_GRAM_INT8;  // no conversion scratch outside the admitted budget
   r.bytes = request_bytes(*p, ldx);
   r.est_us = estimate_us(*p);
   r.t_submit = Clock::now();

@@ -304,10 +304,13 @@ mi_status run_sparse(const mi_problem* p, int64_t ldx, hipStream_t st, bool auto
   HIPCHK(hipStreamSynchronize(st));
   if (auto_choice) {
     // Modelled times (rates measured on this device at 1,000,000 x 4,096):
-    // the dense kernel sustains ~1.4e15 pair-updates/s; the sparse path
-    // reads X twice at ~2.7 TB/s, adds ~2.8e10 pair counts/s (random int32
-    // atomics) and writes the n^2 output.  The count pass already ran.
-    const double dense_s = (double)m * (double)n * ((double)n + 1.0) / 2.0 / 1.4e15;
+    // the dense kernel sustains ~1.4e15 pair-updates/s with the int8 Gram and
+    // ~2.56e15 with the FP4 Gram, after a conversion pass that moves 1.5 bytes
+    // per entry at ~5.1 TB/s; the sparse path reads X twice at ~2.7 TB/s,
+    // adds ~2.8e10 pair counts/s (random int32 atomics) and writes the n^2
+    // output.  The count pass already ran.
+    const double pu = (double)m * (double)n * ((double)n + 1.0) / 2.0;
+    const double dense_s = converts_to_fp4(p) ? pu / 2.56e15 + 1.5 * (double)m * (double)n / 5.1e12 : pu / 1.4e15;
     const double sparse_s = (double)m * (double)ldx / 2.7e12 + (double)npairs / 2.8e10 +
                             4.0 * (double)n * (double)n / 4.0e12;
     if (sparse_s >= dense_s) return MI_OK;  // dense is cheaper: *used stays false

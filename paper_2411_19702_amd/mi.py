@@ -30,6 +30,8 @@ MI_EPI_FP32, MI_EPI_FP32_FP64_FALLBACK, MI_EPI_FP64 = 0, 1, 2
 MI_ALGO_DENSE, MI_ALGO_SPARSE, MI_ALGO_AUTO = 0, 1, 2
 MI_TILE_AUTO, MI_TILE_128, MI_TILE_256 = 0, 1, 2
 MI_BATCH_PERSISTENT, MI_BATCH_GRAPH, MI_BATCH_SEQUENTIAL = 0, 1, 2
+MI_INPUT_BYTES, MI_INPUT_BITS, MI_INPUT_FP4 = 0, 1, 2
+MI_GRAM_AUTO, MI_GRAM_INT8, MI_GRAM_FP4 = 0, 1, 2
 
 
 class MIError(RuntimeError):
@@ -59,6 +61,7 @@ class mi_problem(ctypes.Structure):
         ("pairs_threshold", ctypes.c_float),
         ("algo", ctypes.c_int32),
         ("packed", ctypes.c_int32),
+        ("gram", ctypes.c_int32),
     ]
 
 
@@ -81,6 +84,7 @@ class mi_cat_problem(ctypes.Structure):
         ("pairs_capacity", ctypes.c_int64),
         ("pairs_count", ctypes.c_void_p),
         ("pairs_threshold", ctypes.c_float),
+        ("gram", ctypes.c_int32),
     ]
 
 
@@ -126,6 +130,8 @@ def lib() -> ctypes.CDLL:
         "mi_version": (ctypes.c_char_p, []),
         "mi_cat_problem_init": (None, [P(mi_cat_problem), vp, i64, i64, vp, vp]),
         "mi_pack_bits": (i32, [vp, i64, i64, i64, vp, i64, vp]),
+        "mi_pack_fp4": (i32, [vp, i64, i64, i64, vp, i64, vp]),
+        "mi_plan_ex": (i32, [vp, vp, vp, vp]),
         "mi_cat_indicators": (i32, [vp, i64, P(i64)]),
         "mi_all_pairs_categorical": (i32, [P(mi_cat_problem), vp]),
     }
@@ -153,7 +159,15 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
-def _x_layout(X: torch.Tensor, n: Optional[int], packed: bool = False) -> Tuple[int, int, int]:
+def _layout_code(packed) -> int:
+    """packed: False / MI_INPUT_BYTES, True / MI_INPUT_BITS, or MI_INPUT_FP4."""
+    code = int(packed)
+    if code not in (MI_INPUT_BYTES, MI_INPUT_BITS, MI_INPUT_FP4):
+        raise ValueError(f"bad input layout {packed!r}")
+    return code
+
+
+def _x_layout(X: torch.Tensor, n: Optional[int], packed=False) -> Tuple[int, int, int]:
     if not isinstance(X, torch.Tensor) or X.dim() != 2:
         raise ValueError("X must be a 2-D tensor (rows x columns)")
     if not X.is_cuda:
@@ -164,11 +178,13 @@ def _x_layout(X: torch.Tensor, n: Optional[int], packed: bool = False) -> Tuple[
     if m > 1 and X.stride(1) != 1:
         raise ValueError("X rows must be contiguous (stride(1) == 1)")
     ldx = X.stride(0) if m > 1 else max(cols, 1)
-    if packed:
+    code = _layout_code(packed)
+    if code != MI_INPUT_BYTES:
+        per = 8 if code == MI_INPUT_BITS else 2
         if n is None:
-            raise ValueError("a packed X needs n (its bytes hold 8 columns each)")
-        if (n + 7) // 8 > cols:
-            raise ValueError("n exceeds 8 * X.shape[1]")
+            raise ValueError(f"a packed X needs n (its bytes hold {per} columns each)")
+        if (n + per - 1) // per > cols:
+            raise ValueError(f"n exceeds {per} * X.shape[1]")
         return m, n, ldx
     n = cols if n is None else n
     if n > cols:
@@ -180,9 +196,11 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
                  n11_out: Optional[torch.Tensor] = None, colsum_out: Optional[torch.Tensor] = None,
                  epilogue: int = MI_EPI_FP32, fallback_tau: float = 1e-3, validate: bool = False, tile: int = 0,
                  splits: int = 0, pairs: Optional[torch.Tensor] = None, pairs_count: Optional[torch.Tensor] = None,
-                 pairs_threshold: float = 0.0, algo: int = 0, packed: bool = False) -> mi_problem:
+                 pairs_threshold: float = 0.0, algo: int = 0, packed=False, gram: int = MI_GRAM_AUTO) -> mi_problem:
     """pairs: int32 GPU tensor of shape (capacity, 3) receiving (i, j, MI bits as FP32) rows;
-    pairs_count: int64 GPU tensor with one element (the number of qualifying pairs)."""
+    pairs_count: int64 GPU tensor with one element (the number of qualifying pairs).
+    packed: False (bytes), True / MI_INPUT_BITS (mi_pack_bits) or MI_INPUT_FP4 (mi_pack_fp4).
+    gram: MI_GRAM_AUTO, MI_GRAM_INT8 or MI_GRAM_FP4 (the Gram's matrix instructions)."""
     m, n, ldx = _x_layout(X, n, packed)
     for name, t, dt in (("out", out, torch.float32), ("n11_out", n11_out, torch.int32),
                         ("colsum_out", colsum_out, torch.int32), ("pairs", pairs, torch.int32),
@@ -204,7 +222,8 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
     p.pairs, p.pairs_capacity = _ptr(pairs), (pairs.shape[0] if pairs is not None else 0)
     p.pairs_count, p.pairs_threshold = _ptr(pairs_count), float(pairs_threshold)
     p.algo = int(algo)
-    p.packed = 1 if packed else 0
+    p.packed = _layout_code(packed)
+    p.gram = int(gram)
     return p
 
 
@@ -264,6 +283,15 @@ def mi_plan(m: int, n: int, ldx: int = 0) -> Tuple[int, int]:
     t, s = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().mi_plan(m, n, ldx, ctypes.byref(t), ctypes.byref(s)))
     return t.value, s.value
+
+
+def mi_plan_ex(X: torch.Tensor, n: Optional[int] = None, **kw) -> Tuple[int, int, int]:
+    """(tile, splits, gram) the library would use for this problem (make_problem's keywords;
+    no output needed, nothing launched).  gram is MI_GRAM_INT8 or MI_GRAM_FP4."""
+    p = make_problem(X, None, n=n, **kw)
+    t, s, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mi_plan_ex(ctypes.byref(p), ctypes.byref(t), ctypes.byref(s), ctypes.byref(g)))
+    return t.value, s.value, g.value
 
 
 def mi_tune(m: int, n: int, ldx: int = 0) -> Tuple[int, int, float]:
@@ -367,7 +395,7 @@ def mi_all_pairs_categorical(X: torch.Tensor, levels, out: Optional[torch.Tensor
                              tile: int = 0, splits: int = 0, counts_out: Optional[torch.Tensor] = None,
                              sums_out: Optional[torch.Tensor] = None, stream=None,
                              pairs: Optional[torch.Tensor] = None, pairs_count: Optional[torch.Tensor] = None,
-                             pairs_threshold: float = 0.0, dense: bool = True):
+                             pairs_threshold: float = 0.0, dense: bool = True, gram: int = MI_GRAM_AUTO):
     """MI matrix (v x v FP32, bits) of categorical X: column j holds codes 0 .. levels[j]-1.
     X is a uint8 GPU tensor (m, cols) with contiguous rows; v defaults to cols.
     pairs / pairs_count / pairs_threshold: the sparse output as in make_problem;
@@ -403,7 +431,24 @@ def mi_all_pairs_categorical(X: torch.Tensor, levels, out: Optional[torch.Tensor
     p.counts_out, p.sums_out = _ptr(counts_out), _ptr(sums_out)
     p.pairs, p.pairs_capacity = _ptr(pairs), (pairs.shape[0] if pairs is not None else 0)
     p.pairs_count, p.pairs_threshold = _ptr(pairs_count), float(pairs_threshold)
+    p.gram = int(gram)
     _check(lib().mi_all_pairs_categorical(ctypes.byref(p), _stream_handle(stream)))
+    return out
+
+
+def mi_pack_fp4(X: torch.Tensor, n: Optional[int] = None, out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """Pack a 0/1 byte matrix (m x n) into (m, ceil(n/2)) bytes of FP4 (E2M1) codes: the low nibble of
+    byte c is 0b0010 (1.0) if column 2c is nonzero, else 0; the high nibble likewise for column 2c + 1."""
+    m, n, ldx = _x_layout(X, n)
+    nb = (n + 1) // 2
+    if out is None:
+        out = torch.empty((m, max(nb, 1)), dtype=torch.uint8, device=X.device)
+    if not out.is_cuda or out.dtype != torch.uint8 or out.dim() != 2 or out.shape[0] != m or out.shape[1] < nb \
+            or (m > 1 and out.stride(1) != 1):
+        raise ValueError("out must be a uint8 GPU tensor of shape (m, >= ceil(n/2)) with contiguous rows")
+    ldq = out.stride(0) if m > 1 else max(out.shape[1], 1)
+    _check(lib().mi_pack_fp4(X.data_ptr(), m, n, ldx, out.data_ptr(), ldq, _stream_handle(stream)))
     return out
 
 

@@ -190,6 +190,7 @@ def test_categorical_argument_checks(L):
     assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, ldx=3)), None) == 1
     assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, epilogue=3)), None) == 1
     assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, tile=5)), None) == 1
+    assert L.mi_all_pairs_categorical(ctypes.byref(prob(lv, gram=3)), None) == 1
     empty = mi.mi_cat_problem()
     L.mi_cat_problem_init(ctypes.byref(empty), None, 5, 0, None, None)
     assert L.mi_all_pairs_categorical(ctypes.byref(empty), None) == 0        # v == 0: no-op
@@ -213,6 +214,38 @@ def test_packed_argument_checks(L):
     assert L.mi_pack_bits(16, 10, 17, 17, 32, 2, None) == 1                      # ldp < ceil(n / 8)
     assert L.mi_pack_bits(None, 10, 17, 17, 32, 3, None) == 1
     assert L.mi_pack_bits(16, 0, 17, 17, 32, 3, None) == 0                       # empty: no-op
+
+
+def test_fp4_argument_checks(L):
+    """FP4 input (2 columns per byte) and the Gram choice: pitch in bytes of 2
+    columns and at most 2^23, no validate, no sparse algorithm, no int8 Gram;
+    bit input takes no FP4 Gram; batches run the FP4 Gram on FP4 input only;
+    the packing utility checks its pitches."""
+    from paper_2411_19702_amd import mi
+    def prob(**kw):
+        p = mi.mi_problem()
+        p.X, p.m, p.n, p.out, p.packed, p.ldx = 16, 10, 17, 32, mi.MI_INPUT_FP4, 9
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+    ex = lambda **kw: L.mi_all_pairs_ex(ctypes.byref(prob(**kw)), None)
+    assert ex(ldx=8) == 1                                      # 17 columns need 9 bytes
+    assert ex(gram=mi.MI_GRAM_INT8) == 1                       # FP4 input, int8 Gram
+    assert ex(validate=1) == 1
+    assert ex(algo=mi.MI_ALGO_SPARSE) == 1
+    assert ex(ldx=(1 << 23) + 16) == 1                         # 128-row stages, 32-bit offsets
+    assert ex(packed=3) == 1 and ex(gram=3) == 1 and ex(gram=-1) == 1
+    assert ex(packed=mi.MI_INPUT_BITS, ldx=3, gram=mi.MI_GRAM_FP4) == 1
+    assert ex(packed=mi.MI_INPUT_BYTES, ldx=17, gram=mi.MI_GRAM_FP4, algo=mi.MI_ALGO_SPARSE) == 1
+    for mode in (mi.MI_BATCH_PERSISTENT, mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL):
+        arr = (mi.mi_problem * 1)(prob(packed=mi.MI_INPUT_BYTES, ldx=17, gram=mi.MI_GRAM_FP4))
+        assert L.mi_all_pairs_batched(arr, 1, None, mode) == 1    # conversion is not done in batches
+    arr = (mi.mi_problem * 1)(prob())
+    assert L.mi_all_pairs_batched(arr, 1, None, mi.MI_BATCH_PERSISTENT) == 1
+    assert L.mi_pack_fp4(16, 10, 17, 16, 32, 9, None) == 1     # ldx < n
+    assert L.mi_pack_fp4(16, 10, 17, 17, 32, 8, None) == 1     # ldq < ceil(n / 2)
+    assert L.mi_pack_fp4(None, 10, 17, 17, 32, 9, None) == 1
+    assert L.mi_pack_fp4(16, 0, 17, 17, 32, 9, None) == 0      # empty: no-op
 
 
 def test_column_limit(L):

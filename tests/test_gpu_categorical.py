@@ -193,14 +193,37 @@ def test_categorical_side_stream():
     assert np.array_equal(out.cpu().numpy(), _run(X, levels))
 
 
+@pytest.mark.parametrize("seed,m,v,lmin,lmax,pitch", CASES + [(7, 3000, 900, 2, 4, None), (8, 1500, 333, 1, 7, 341)])
+def test_categorical_fp4_gram_equals_int8(seed, m, v, lmin, lmax, pitch):
+    """Indicators expanded straight into the FP4 layout and counted on the FP4
+    matrix cores: counts, sums and MI bitwise equal to the int8 Gram's."""
+    say(f"[cat fp4] seed={seed} {m}x{v} levels {lmin}..{lmax} pitch={pitch}")
+    spec = synth.spec_categorical(seed, m, v, lmin, lmax, ldx=pitch, planted=max(1, v // 25))
+    X = synth.cat_generate(spec, device=DEV)
+    levels = [int(x) for x in spec.levels]
+    N = mi.mi_cat_indicators(levels)
+    res = []
+    for g in (mi.MI_GRAM_INT8, mi.MI_GRAM_FP4):
+        G = torch.full((max(N, 1), max(N, 1)), -1, dtype=torch.int32, device=DEV)
+        S = torch.full((max(N, 1),), -1, dtype=torch.int32, device=DEV)
+        out = torch.full((v, v), float("nan"), device=DEV)
+        mi.mi_all_pairs_categorical(X, levels, out=out, v=v, counts_out=G, sums_out=S, gram=g)
+        torch.cuda.synchronize()
+        res.append((out, G, S))
+    for a, b in zip(res[0], res[1]):
+        assert torch.equal(a, b)
+
+
 def test_genotype_workload_sampled():
     """The full-size genotype workload (1,000,000 x 2,048, 3 codes) in the
-    configuration the benchmark times; sampled pairs against the oracle."""
+    configuration the benchmark times (the FP4 Gram at this shape); sampled
+    pairs against the oracle, every pair bitwise against the int8 Gram."""
     spec = synth.spec_genotypes()
     say(f"[cat] genotypes {spec.m}x{spec.v}")
     X = synth.cat_generate(spec, device=DEV)
     levels = [int(x) for x in spec.levels]
     got = _run(X, levels)
+    assert np.array_equal(got, _run(X, levels, gram=mi.MI_GRAM_INT8))
     rng = np.random.default_rng(19)
     cols = sorted(set(rng.choice(spec.v, size=10, replace=False).tolist()) |
                   {spec.planted[0][0], spec.planted[0][1]})

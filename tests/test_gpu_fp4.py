@@ -1,0 +1,181 @@
+"""GPU: the FP4 Gram (E2M1 operands, FP32 accumulation) against the int8 Gram
+and the oracle.
+
+A 0/1 entry is the E2M1 code of 1.0 or 0, so every product is exactly 0 or 1
+and the FP32 accumulator holds the exact count while it stays below 2^24 (a
+unit covers at most 2^24 rows).  The counts, hence every output, must then be
+bitwise identical to the int8 path's; small cases are also checked against the
+FP64 oracle.  The FP4 packing utility must equal a numpy nibble packing.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2411_19702_amd import mi, synth
+from tests.gpu_util import compare_full, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _pack_ref(Xh, n):
+    nz = (Xh[:, :n] != 0).astype(np.uint8) * 2
+    if n % 2:
+        nz = np.concatenate([nz, np.zeros((nz.shape[0], 1), np.uint8)], axis=1)
+    return (nz[:, 0::2] | (nz[:, 1::2] << 4)).astype(np.uint8)
+
+
+def _run(X, n, **kw):
+    out = torch.full((n, n), float("nan"), device=DEV)
+    n11 = torch.full((n, n), -1, dtype=torch.int32, device=DEV)
+    cs = torch.full((max(n, 1),), -1, dtype=torch.int32, device=DEV)
+    mi.mi_all_pairs_ex(X, out=out, n=n, n11_out=n11, colsum_out=cs, **kw)
+    torch.cuda.synchronize()
+    return out, n11, cs
+
+
+def _same(a, b, what=""):
+    for x, y, name in zip(a, b, ("MI", "n11", "column sums")):
+        assert torch.equal(x, y), f"{what}: FP4 {name} differ from the int8 Gram"
+
+
+@pytest.mark.parametrize("m,n,pitch", [(5, 1, None), (100, 7, None), (1000, 64, None), (777, 129, 160),
+                                       (300, 1000, 1003), (2, 4096, None), (70, 33, None)])
+def test_pack_fp4_matches_numpy(m, n, pitch):
+    say(f"[fp4 pack] {m}x{n} pitch={pitch}")
+    spec = synth.spec_random(61 + n, m, n, 0.0, 1.0, ldx=pitch)
+    X = synth.generate(spec, device=DEV)[:, :n]
+    Q = mi.mi_pack_fp4(X, n)
+    torch.cuda.synchronize()
+    nb = (n + 1) // 2
+    assert np.array_equal(Q.cpu().numpy()[:, :nb], _pack_ref(X.cpu().numpy(), n))
+    # a pitched, unaligned destination; its bytes past ceil(n / 2) stay untouched
+    W = torch.full((m, nb + 21), 0xAB, dtype=torch.uint8, device=DEV)
+    mi.mi_pack_fp4(X, n, out=W[:, 3:3 + nb])
+    torch.cuda.synchronize()
+    Wh = W.cpu().numpy()
+    assert np.array_equal(Wh[:, 3:3 + nb], _pack_ref(X.cpu().numpy(), n))
+    assert (Wh[:, :3] == 0xAB).all() and (Wh[:, 3 + nb:] == 0xAB).all()
+
+
+CASES = [  # (m, n): one and several 128-row stages, ragged rows and columns, several tiles
+    (1, 1), (3, 2), (63, 17), (128, 16), (129, 129), (200, 300), (1000, 257), (4097, 130), (129, 385),
+    (1000, 200), (20000, 1000), (515, 513),
+]
+
+
+@pytest.mark.parametrize("m,n", CASES)
+@pytest.mark.parametrize("epi", [0, 2])
+def test_fp4_gram_equals_int8(m, n, epi):
+    say(f"[fp4] {m}x{n} epi={epi}")
+    spec = synth.spec_random(11 * m + n, m, n, 0.0, 1.0, planted=max(1, n // 20))
+    X = synth.generate(spec, device=DEV)
+    b = _run(X, n, epilogue=epi, gram=mi.MI_GRAM_INT8)
+    f = _run(X, n, epilogue=epi, gram=mi.MI_GRAM_FP4)
+    _same(b, f, "converted bytes")
+    Q = mi.mi_pack_fp4(X, n)
+    q = _run(Q, n, epilogue=epi, packed=mi.MI_INPUT_FP4)
+    _same(b, q, "FP4 input")
+    if m * n <= 1_000_000:
+        compare_full(X.cpu().numpy(), n, f[0].cpu().numpy(), f[1].cpu().numpy(), f[2].cpu().numpy()[:n])
+
+
+@pytest.mark.parametrize("tile,splits", [(1, 1), (2, 1), (1, 5), (2, 3), (2, 7)])
+def test_fp4_configurations(tile, splits):
+    say(f"[fp4] tile={tile} splits={splits}")
+    spec = synth.spec_random(71, 30000, 700, 0.0, 0.5, planted=10)
+    X = synth.generate(spec, device=DEV)
+    b = _run(X, 700, tile=tile, splits=splits, gram=mi.MI_GRAM_INT8)
+    f = _run(X, 700, tile=tile, splits=splits, gram=mi.MI_GRAM_FP4)
+    _same(b, f, f"tile {tile} splits {splits}")
+
+
+def test_fp4_unaligned_inputs_and_counts_only():
+    say("[fp4] unaligned byte and FP4 inputs, counts-only output")
+    spec = synth.spec_random(73, 5000, 333, 0.0, 0.7, planted=5)
+    X = synth.generate(spec, device=DEV)
+    b = _run(X, 333, gram=mi.MI_GRAM_INT8)
+    wide = torch.zeros((5000, 333 + 9), dtype=torch.uint8, device=DEV)
+    Xu = wide[:, 1:334]                      # bytes: base off by one, pitch 342
+    Xu.copy_(X[:, :333])
+    _same(b, _run(Xu, 333, gram=mi.MI_GRAM_FP4), "unaligned bytes")
+    nb = (333 + 1) // 2
+    Qw = torch.zeros((5000, nb + 7), dtype=torch.uint8, device=DEV)
+    Qu = Qw[:, 3:3 + nb]                     # FP4: base off by 3, pitch nb + 7 (repacked)
+    mi.mi_pack_fp4(X, 333, out=Qu)
+    _same(b, _run(Qu, 333, packed=mi.MI_INPUT_FP4), "unaligned FP4")
+    n11 = torch.empty((333, 333), dtype=torch.int32, device=DEV)
+    mi.mi_all_pairs_ex(X, out=None, dense=False, n11_out=n11, gram=mi.MI_GRAM_FP4)
+    torch.cuda.synchronize()
+    assert torch.equal(n11, b[1])
+
+
+def test_fp4_large_workload_equals_int8():
+    """The 1,000,000 x 4,096 workload: the library's choice (FP4 at this shape)
+    and both explicit Grams give bitwise the same MI matrix."""
+    spec = synth.spec_large()
+    say(f"[fp4] {spec.m}x{spec.n}")
+    X = synth.generate(spec, device=DEV)
+    outs = []
+    for g in (mi.MI_GRAM_INT8, mi.MI_GRAM_FP4, mi.MI_GRAM_AUTO):
+        o = torch.empty((spec.n, spec.n), device=DEV)
+        mi.mi_all_pairs_ex(X, out=o, gram=g)
+        outs.append(o)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+def test_fp4_units_stay_below_2_24_rows():
+    """m = 2^24 + 2^22 rows with one split requested: the library splits the
+    rows so that no FP32 accumulator exceeds 2^24, and the counts stay exact
+    (column sums above 2^24 included)."""
+    m, n = (1 << 24) + (1 << 22), 40
+    say(f"[fp4] {m}x{n}, splits=1 requested")
+    g = torch.Generator(device=DEV)
+    g.manual_seed(5)
+    p = torch.linspace(0.8, 0.99, n, device=DEV)
+    X = (torch.rand((m, n), generator=g, device=DEV) < p).to(torch.uint8)
+    b = _run(X, n, splits=1, gram=mi.MI_GRAM_INT8)
+    f = _run(X, n, splits=1, gram=mi.MI_GRAM_FP4)
+    _same(b, f, "2^24 + 2^22 rows")
+    cs = X.sum(dim=0, dtype=torch.int64)
+    assert torch.equal(f[2].to(torch.int64), cs)
+    assert int(cs.max()) > (1 << 24), "the case must hold counts above 2^24"
+
+
+@pytest.mark.parametrize("mode", [mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL])
+def test_fp4_input_in_batches(mode):
+    """FP4 and byte problems in one graph / sequential batch: each equal to its single call."""
+    say(f"[fp4] batch mode {mode}")
+    specs = [synth.spec_random(950 + k, 2000 + 900 * k, 70 + 53 * k, 0.0, 0.8, planted=3) for k in range(4)]
+    Xs = [synth.generate(s, device=DEV) for s in specs]
+    outs = [torch.full((s.n, s.n), float("nan"), device=DEV) for s in specs]
+    probs, keep = [], []  # problems hold raw pointers: keep the packed tensors alive
+    for k, (s, X, o) in enumerate(zip(specs, Xs, outs)):
+        if k % 2 == 0:
+            keep.append(mi.mi_pack_fp4(X))
+            probs.append(mi.make_problem(keep[-1], o, n=s.n, packed=mi.MI_INPUT_FP4))
+        else:
+            probs.append(mi.make_problem(X, o))
+    for _ in range(2):  # the graph mode replays its cached graph the second time
+        for o in outs:
+            o.fill_(float("nan"))
+        mi.mi_all_pairs_batched(probs, mode=mode)
+        torch.cuda.synchronize()
+        for X, o in zip(Xs, outs):
+            want = torch.empty_like(o)
+            mi.mi_all_pairs_ex(X, out=want, gram=mi.MI_GRAM_INT8)
+            torch.cuda.synchronize()
+            assert torch.equal(o, want)
+
+
+def test_fp4_rejected_where_unsupported():
+    X = torch.zeros((10, 40), dtype=torch.uint8, device=DEV)
+    out = torch.empty((40, 40), device=DEV)
+    with pytest.raises(mi.MIError):
+        mi.mi_all_pairs_ex(X, out=out, gram=mi.MI_GRAM_FP4, algo=mi.MI_ALGO_SPARSE)
+    with pytest.raises(mi.MIError):
+        mi.mi_all_pairs_ex(mi.mi_pack_fp4(X), out=out, n=40, packed=mi.MI_INPUT_FP4, validate=True)
+    with mi.Server(hbm_budget_bytes=1 << 30) as srv:
+        with pytest.raises(mi.MIError):
+            srv.submit(X, out, gram=mi.MI_GRAM_FP4)
