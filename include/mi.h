@@ -99,9 +99,9 @@ typedef enum mi_input {
  * whose 1.0 products sum to integers in the FP32 accumulator; each work unit
  * then covers at most 2^24 rows, so every partial count is exact. */
 typedef enum mi_gram {
-  MI_GRAM_AUTO = 0,  /* the library's choice: FP4 for byte input when the Gram dominates  */
-                     /* (byte input is first converted to the FP4 layout in scratch      */
-                     /* memory, half the input's size), int8 otherwise                   */
+  MI_GRAM_AUTO = 0,  /* the library's choice: FP4 for byte input with n >= 1536 and       */
+                     /* m n^2 >= 6e10 (converted to the FP4 layout first, in scratch     */
+                     /* memory of half the input's size), int8 otherwise                 */
   MI_GRAM_INT8 = 1,  /* v_mfma_i32_32x32x32_i8 on bytes (or unpacked bits)                */
   MI_GRAM_FP4 = 2    /* v_mfma_scale_f32_32x32x64_f8f6f4 on E2M1 codes: twice the samples */
                      /* per byte staged and ~1.7x the int8 instruction rate               */

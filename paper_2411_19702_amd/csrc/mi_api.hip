@@ -270,13 +270,15 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
   return MI_OK;
 }
 
-// The FP4 Gram for byte input when the library chooses: the conversion pass
-// (read the input, write half of it) costs about m n 1.5 B at HBM speed, and
-// the Gram saves about 40% of m n (n + 1) / 2 pair-updates at ~1.5e15 per
-// second; the saving exceeds the pass from about 1,500 columns on.  With few
-// rows the FP4 Gram still wins (half the 64-row steps, each with a fixed
-// cost: 0.160 against 0.177 ms at 2,000 x 8,192, conversion included).
-bool fp4_preferred(int64_t m, int64_t n) { return n >= 1536 && m >= 1024; }
+// The FP4 Gram for byte input when the library chooses.  The conversion pass
+// (read the input, write half of it) costs one launch plus m n 1.5 B at HBM
+// speed; the FP4 Gram halves the row steps and runs its instruction ~1.7x
+// faster.  Measured (conversion included, against the int8 Gram): 0.95-0.98x
+// up to m n^2 ~ 3.4e10 (2,000 x 4,096; 5,000 x 2,048), 1.00x at 1.7e11
+// (10,000 x 4,096), 1.06-1.07x from 6.7e10 (1,000 x 8,192; 20,000 x 2,048),
+// 1.33x at 50,000 x 4,096 and 1,000,000 x 4,096 (1.25x); at 1,024 columns
+// the two tie (100,000 x 1,024).
+bool fp4_preferred(int64_t m, int64_t n) { return n >= 1536 && (double)m * (double)n * (double)n >= 6.0e10; }
 
 // Byte input converted to the FP4 layout first (requested, or the library's choice).
 bool converts_to_fp4(const mi_problem* p) {
