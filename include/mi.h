@@ -147,13 +147,14 @@ typedef struct mi_problem {
    * column 2 c in the low nibble of byte c, each nibble 0b0010 (a one) or 0
    * (as mi_pack_fp4 writes them; other codes give undefined counts); ldx >=
    * ceil(n / 2), at most 2^23; validate must be 0.  Results are the same as
-   * for the byte layout.  Packed layouts take the dense algorithm only, in
-   * single calls and the graph / sequential batch modes (not the persistent
-   * mode or the server). */
+   * for the byte layout.  Packed layouts take the dense algorithm only; bits
+   * in single calls and the graph / sequential batch modes, FP4 in single
+   * calls and every batch mode; the server takes neither. */
   int32_t packed;
   /* mi_gram.  MI_GRAM_FP4 needs byte or FP4 input; MI_GRAM_INT8 byte or bit
-   * input.  The persistent batch mode and the server use the int8 Gram
-   * (MI_GRAM_AUTO) and reject MI_GRAM_FP4. */
+   * input.  Batches follow each problem's choice (byte input converted in
+   * the batch's scratch).  The server runs the int8 Gram and rejects
+   * MI_GRAM_FP4 (its HBM budget holds no conversion buffer). */
   int32_t gram;
 } mi_problem;
 

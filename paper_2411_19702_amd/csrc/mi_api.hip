@@ -50,7 +50,8 @@ mi_status device_info(DeviceInfo* out) {
     HIPCHK(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
     for (int c = 0; c < kNumCfg; ++c) {
       di.occ[c] = occupancy(c);
-      di.pocc[c] = persistent_occupancy(c);
+      di.pocc[c][0] = persistent_occupancy(c, false);
+      di.pocc[c][1] = persistent_occupancy(c, true);
     }
     it = g_info.emplace(dev, di).first;
   }
@@ -478,7 +479,7 @@ static std::string batch_key(const mi_problem* probs, int64_t count, const std::
              p.epilogue, (double)p.fallback_tau, plans[d].cfg, plans[d].splits, (void*)p.pairs,
              (long long)p.pairs_capacity, (void*)p.pairs_count, (double)p.pairs_threshold);
     k += buf;
-    snprintf(buf, sizeof buf, "%d;", p.packed);
+    snprintf(buf, sizeof buf, "%d,%d;", p.packed, converts_to_fp4(&p) ? 1 : 0);
     k += buf;
   }
   return k;
@@ -502,11 +503,15 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     if (probs[d].validate) return fail(MI_ERR_INVALID_ARG, "problem %lld: validate is not supported in batches", (long long)d);
     if (probs[d].algo != MI_ALGO_DENSE)
       return fail(MI_ERR_INVALID_ARG, "problem %lld: batches take only the dense algorithm", (long long)d);
-    if (probs[d].packed && mode == MI_BATCH_PERSISTENT)
-      return fail(MI_ERR_INVALID_ARG, "problem %lld: the persistent mode takes only the byte layout", (long long)d);
-    if (probs[d].gram == MI_GRAM_FP4 && probs[d].packed != MI_INPUT_FP4)
-      return fail(MI_ERR_INVALID_ARG,
-                  "problem %lld: batches run the FP4 Gram on FP4 input only (pack it with mi_pack_fp4)", (long long)d);
+    if (probs[d].packed == MI_INPUT_BITS && mode == MI_BATCH_PERSISTENT)
+      return fail(MI_ERR_INVALID_ARG, "problem %lld: the persistent mode takes bytes or FP4 input, not bits",
+                  (long long)d);
+  }
+  // Per dataset: converted from bytes to the FP4 layout first, and run on the FP4 Gram.
+  std::vector<char> conv(count), f4(count);
+  for (int64_t d = 0; d < count; ++d) {
+    conv[d] = converts_to_fp4(&probs[d]) ? 1 : 0;
+    f4[d] = (conv[d] || probs[d].packed == MI_INPUT_FP4) ? 1 : 0;
   }
   DeviceInfo di;
   s = device_info(&di);
@@ -536,12 +541,12 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
       if (probs[d].n == 0) continue;
       Plan p0;
       const int tile = probs[d].tile != MI_TILE_AUTO ? probs[d].tile : batch_tile;
-      s = choose_plan(probs[d].m, probs[d].n, aligned[d], tile, 1, &p0);
+      s = choose_plan(probs[d].m, probs[d].n, aligned[d] || conv[d], tile, 1, &p0, f4[d]);
       if (s != MI_OK) return s;
       total += (double)p0.ntiles * p0.bt * p0.bt * (double)probs[d].m;
       plans[d] = p0;
     }
-    const double slots = (double)di.cus * di.pocc[0];
+    const double slots = (double)di.cus * di.pocc[0][0];
     const double target = std::max(total / (slots * 4.0), 1.0);
     for (int64_t d = 0; d < count; ++d) {
       if (probs[d].n == 0) continue;
@@ -552,26 +557,31 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
         sp = std::max(sp, 1);
       }
       plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].cfg, sp);
+      while (f4[d] && plans[d].kchunk > kFp4MaxUnitRows)  // exact FP32 counts
+        plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].cfg, plans[d].splits + 1);
     }
   } else {
     for (int64_t d = 0; d < count; ++d) {
       if (probs[d].n == 0) continue;
-      s = choose_plan(probs[d].m, probs[d].n, aligned[d], probs[d].tile, probs[d].splits, &plans[d],
-                      probs[d].packed == MI_INPUT_FP4);
+      s = choose_plan(probs[d].m, probs[d].n, aligned[d] || conv[d], probs[d].tile, probs[d].splits, &plans[d],
+                      f4[d]);
       if (s != MI_OK) return s;
     }
   }
 
-  // One split-K workspace and one repack buffer hold every dataset's region.
+  // One split-K workspace and one buffer for the repacked and converted
+  // inputs hold every dataset's region.  ld_in[d]: the pitch the kernel reads.
   std::vector<size_t> ws_off(count, 0), rp_off(count, 0);
+  std::vector<int64_t> ld_in(count, 0);
   size_t ws_total = 0, rp_total = 0;
   for (int64_t d = 0; d < count; ++d) {
     if (probs[d].n == 0) continue;
     ws_off[d] = ws_total;
     ws_total += (workspace_bytes(plans[d]) + 255) & ~(size_t)255;
-    if (!aligned[d]) {
+    ld_in[d] = conv[d] ? packed_pitch((probs[d].n + 1) / 2) : (aligned[d] ? ldx[d] : packed_pitch(row_bytes(probs[d])));
+    if (conv[d] || !aligned[d]) {
       rp_off[d] = rp_total;
-      rp_total += ((size_t)probs[d].m * (size_t)packed_pitch(row_bytes(probs[d])) + 255) & ~(size_t)255;
+      rp_total += ((size_t)probs[d].m * (size_t)ld_in[d] + 255) & ~(size_t)255;
     }
   }
   void* ws = nullptr;
@@ -586,14 +596,22 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     hipError_t e;
     const int32_t* tiles = tile_table(plans[d].ntp, &e);
     if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(e));
-    const uint8_t* X = aligned[d] ? probs[d].X : (const uint8_t*)rp + rp_off[d];
-    const int64_t ld = aligned[d] ? ldx[d] : packed_pitch(row_bytes(probs[d]));
-    P[d] = make_probdev(&probs[d], X, ld, plans[d], ws ? (char*)ws + ws_off[d] : nullptr, tiles);
+    const uint8_t* X = (aligned[d] && !conv[d]) ? probs[d].X : (const uint8_t*)rp + rp_off[d];
+    mi_problem q = probs[d];  // the problem as the kernel sees it
+    if (conv[d]) q.packed = MI_INPUT_FP4;
+    P[d] = make_probdev(&q, X, ld_in[d], plans[d], ws ? (char*)ws + ws_off[d] : nullptr, tiles);
   }
+  // The input staging of dataset d (conversion or repack), if it has one.
+  auto stage_input = [&](int64_t d, hipStream_t s_) -> hipError_t {
+    if (conv[d]) return launch_pack_fp4(probs[d].X, probs[d].m, probs[d].n, ldx[d], (uint8_t*)P[d].X, P[d].ldx, s_);
+    if (!aligned[d])
+      return launch_repack(probs[d].X, probs[d].m, row_bytes(probs[d]), ldx[d], (uint8_t*)P[d].X, P[d].ldx, s_);
+    return hipSuccess;
+  };
   auto repack_all = [&]() -> hipError_t {
     for (int64_t d = 0; d < count; ++d) {
-      if (probs[d].n == 0 || aligned[d]) continue;
-      hipError_t e = launch_repack(probs[d].X, probs[d].m, row_bytes(probs[d]), ldx[d], (uint8_t*)P[d].X, P[d].ldx, st);
+      if (probs[d].n == 0) continue;
+      hipError_t e = stage_input(d, st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -637,8 +655,7 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
       for (int64_t d = 0; d < count && e == hipSuccess; ++d) {
         if (probs[d].pairs) e = fill_i32(reinterpret_cast<int*>(probs[d].pairs_count), 0, 2, cap);
         if (e != hipSuccess || probs[d].n == 0) continue;
-        if (!aligned[d])
-          e = launch_repack(probs[d].X, probs[d].m, row_bytes(probs[d]), ldx[d], (uint8_t*)P[d].X, P[d].ldx, cap);
+        e = stage_input(d, cap);
         if (e == hipSuccess) e = launch_plain(plans[d].cfg, P[d], cap);
       }
       if (e != hipSuccess) {
@@ -662,14 +679,20 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
     return MI_OK;
   }
 
-  // Persistent: work list sorted by decreasing unit rows, one launch per tile size.
-  std::vector<UnitRef> units[kNumCfg];
+  // Persistent: work lists sorted by decreasing unit rows, one launch per tile
+  // size and Gram (list g * kNumCfg + c; the FP4 lists, which hold the
+  // largest datasets, launch first).
+  constexpr int kLists = 2 * kNumCfg;
+  const int order[kLists] = {kNumCfg + 1, kNumCfg + 0, 1, 0};
+  static_assert(kNumCfg == 2, "launch order lists every (Gram, tile) pair");
+  std::vector<UnitRef> units[kLists];
   for (int64_t d = 0; d < count; ++d) {
     if (probs[d].n == 0) continue;
+    const int li = (f4[d] ? kNumCfg : 0) + plans[d].cfg;
     for (int sp = 0; sp < plans[d].splits; ++sp)
-      for (int t = 0; t < plans[d].ntiles; ++t) units[plans[d].cfg].push_back(UnitRef{(int32_t)d, t, sp, 0});
+      for (int t = 0; t < plans[d].ntiles; ++t) units[li].push_back(UnitRef{(int32_t)d, t, sp, 0});
   }
-  for (int c = 0; c < kNumCfg; ++c) {
+  for (int c = 0; c < kLists; ++c) {
     std::stable_sort(units[c].begin(), units[c].end(), [&](const UnitRef& x, const UnitRef& y) {
       const int64_t rx = std::min<int64_t>(P[x.prob].kchunk, P[x.prob].m - (int64_t)x.split * P[x.prob].kchunk);
       const int64_t ry = std::min<int64_t>(P[y.prob].kchunk, P[y.prob].m - (int64_t)y.split * P[y.prob].kchunk);
@@ -678,18 +701,20 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   }
   const size_t probs_bytes = ((sizeof(ProbDev) * count) + 255) & ~(size_t)255;
   size_t nunits = 0;
-  for (int c = 0; c < kNumCfg; ++c) nunits += units[c].size();
+  for (int c = 0; c < kLists; ++c) nunits += units[c].size();
   const size_t units_bytes = ((sizeof(UnitRef) * nunits) + 255) & ~(size_t)255;
   // Every repack of the batch runs as one launch from a descriptor list.
   std::vector<RepackDesc> rdesc;
   int64_t rblocks = 0;
   for (int64_t d = 0; d < count; ++d) {
-    if (probs[d].n == 0 || aligned[d]) continue;
+    if (probs[d].n == 0 || (aligned[d] && !conv[d])) continue;
     // At most 2^22 blocks in all (the grid stays far below 2^32 work-items);
-    // layouts with fewer blocks than their chunks loop.
+    // layouts with fewer blocks than their chunks loop.  A conversion reads
+    // the n byte columns; a repack copies the row's bytes.
     const int64_t cap = std::max<int64_t>(1, ((int64_t)1 << 22) / count);
-    RepackDesc r{probs[d].X, ldx[d], (uint8_t*)P[d].X, P[d].ldx, probs[d].m, probs[d].n, rblocks,
-                 std::min<int64_t>(repack_blocks(probs[d].m, P[d].ldx), cap)};
+    RepackDesc r{probs[d].X, ldx[d], (uint8_t*)P[d].X, P[d].ldx, probs[d].m,
+                 conv[d] ? probs[d].n : row_bytes(probs[d]), rblocks,
+                 std::min<int64_t>(repack_blocks(probs[d].m, P[d].ldx), cap), conv[d] ? 1 : 0, 0};
     rblocks += r.blocks;
     rdesc.push_back(r);
   }
@@ -723,9 +748,9 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   char* h = (char*)bb.host;
   std::memcpy(h, P.data(), sizeof(ProbDev) * count);
   size_t uoff = probs_bytes;
-  for (int c = 0; c < kNumCfg; ++c) {
-    std::memcpy(h + uoff, units[c].data(), sizeof(UnitRef) * units[c].size());
-    uoff += sizeof(UnitRef) * units[c].size();
+  for (int li : order) {
+    std::memcpy(h + uoff, units[li].data(), sizeof(UnitRef) * units[li].size());
+    uoff += sizeof(UnitRef) * units[li].size();
   }
   if (!rdesc.empty()) std::memcpy(h + probs_bytes + units_bytes, rdesc.data(), sizeof(RepackDesc) * rdesc.size());
   HIPCHK(hipMemcpyAsync(bb.dev, bb.host, probs_bytes + units_bytes + rdesc_bytes, hipMemcpyHostToDevice, st));
@@ -737,10 +762,11 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   const ProbDev* dP = (const ProbDev*)dv;
   const UnitRef* dU = (const UnitRef*)(dv + probs_bytes);
   int* head = (int*)(dv + probs_bytes + units_bytes + rdesc_bytes);
-  for (int c = 0; c < kNumCfg; ++c) {
-    const int64_t grid = std::min<int64_t>((int64_t)di.cus * di.pocc[c], (int64_t)units[c].size());
-    HIPCHK(launch_persistent(c, dP, dU, (int)units[c].size(), head + c, (int)grid, st));
-    dU += units[c].size();
+  for (int li : order) {
+    const int c = li % kNumCfg, g = li / kNumCfg;
+    const int64_t grid = std::min<int64_t>((int64_t)di.cus * di.pocc[c][g], (int64_t)units[li].size());
+    HIPCHK(launch_persistent(c, g == 1, dP, dU, (int)units[li].size(), head + li, (int)grid, st));
+    dU += units[li].size();
   }
   return MI_OK;
 }

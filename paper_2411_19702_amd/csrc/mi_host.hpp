@@ -23,7 +23,7 @@ struct DeviceInfo {
   int device = 0;
   int cus = 0;
   int occ[kNumCfg] = {1, 1};   // plain kernel workgroups per CU, per configuration
-  int pocc[kNumCfg] = {1, 1};  // persistent kernel workgroups per CU
+  int pocc[kNumCfg][2] = {{1, 1}, {1, 1}};  // persistent kernel workgroups per CU [cfg][int8, FP4]
 };
 
 struct Plan {

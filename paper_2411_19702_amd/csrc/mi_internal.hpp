@@ -25,6 +25,8 @@ struct RepackDesc {
   int64_t m, n;
   int64_t first_block;  // batched launch: first block of this layout
   int64_t blocks;       // blocks that work on this layout
+  int32_t fp4;          // nonzero: convert bytes (n columns) to the FP4 layout instead of copying
+  int32_t pad;
 };
 
 // Tile configurations: 0 = 128 x 128 (Cfg128), 1 = 256 x 256 (Cfg256).
@@ -33,8 +35,8 @@ int cfg_tile(int cfg);
 int cfg_threads(int cfg);
 
 hipError_t launch_plain(int cfg, const ProbDev& P, hipStream_t st);
-hipError_t launch_persistent(int cfg, const ProbDev* probs, const UnitRef* units, int nunits, int* head, int grid,
-                             hipStream_t st);
+hipError_t launch_persistent(int cfg, bool fp4, const ProbDev* probs, const UnitRef* units, int nunits, int* head,
+                             int grid, hipStream_t st);
 hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st);
 hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Y, int64_t ldy,
                          hipStream_t st);
@@ -46,6 +48,6 @@ hipError_t launch_pack_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, 
                            hipStream_t st);
 hipError_t fill_i32(int* p, int v, int count, hipStream_t st);
 int occupancy(int cfg);
-int persistent_occupancy(int cfg);
+int persistent_occupancy(int cfg, bool fp4);
 
 }  // namespace mi

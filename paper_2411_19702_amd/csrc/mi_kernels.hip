@@ -35,8 +35,10 @@ __global__ __launch_bounds__(C::NT) void k_plain(ProbDev P) {
   run_unit<C, IN>(P, t, k0, min(P.m, k0 + P.kchunk), sm);
 }
 
-// Persistent workgroups pull units of many datasets from a device queue.
-template <class C>
+// Persistent workgroups pull units of many datasets from a device queue.  IN:
+// the input layout of every dataset of the launch (bytes: int8 Gram, FP4: FP4
+// Gram); a batch with both runs one launch of each.
+template <class C, int IN>
 __global__ __launch_bounds__(C::NT) void k_persistent(const ProbDev* __restrict__ probs,
                                                       const UnitRef* __restrict__ units, int nunits,
                                                       int* __restrict__ head) {
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(C::NT) void k_persistent(const ProbDev* __restrict_
     const UnitRef ur = units[u];
     const ProbDev P = probs[ur.prob];
     const int k0 = ur.split * P.kchunk;
-    run_unit<C>(P, ur.tile, k0, min(P.m, k0 + P.kchunk), sm);
+    run_unit<C, IN>(P, ur.tile, k0, min(P.m, k0 + P.kchunk), sm);
     __syncthreads();
   }
 }
@@ -69,6 +71,64 @@ __global__ void k_validate(const uint8_t* __restrict__ X, int64_t m, int64_t n, 
     for (int64_t c = threadIdx.x; c < n; c += blockDim.x) bad |= (r[c] > 1);
   }
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// Byte -> FP4 packing (the layout of the FP4 path): two columns per byte,
+// column 2 c in the low nibble of byte c, the E2M1 code of 1.0 (0b0010) for a
+// nonzero byte and 0 for a zero.  Four input bytes give 16 output bits: bit 7
+// of each nonzero byte (a carry-free nonzero test) moves to bit 1 of
+// its nibble.
+__device__ __forceinline__ uint32_t fp4_of(uint32_t d) {
+  const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
+  return ((nz >> 6) & 0x2u) | ((nz >> 10) & 0x20u) | ((nz >> 14) & 0x200u) | ((nz >> 18) & 0x2000u);
+}
+
+// FP4 codes of 32 columns from src (avail = columns of the row from src on;
+// those past it are 0), as 16 bytes.  A 16-byte-aligned source inside the
+// row is two 16-byte loads; otherwise, when the nine aligned dwords around it
+// lie inside X ([xbeg, xend) = first to one past the last byte read), they
+// are loaded and shifted into place with v_alignbyte (as the repack does);
+// anything else goes byte by byte.
+__device__ __forceinline__ uint4 fp4_pack32(const uint8_t* src, int64_t avail, const uint8_t* xbeg,
+                                            const uint8_t* xend) {
+  uint32_t w[8];
+  const uint8_t* lo = reinterpret_cast<const uint8_t*>(reinterpret_cast<uintptr_t>(src) & ~(uintptr_t)3);
+  if (avail >= 32 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    const uint4 a = *reinterpret_cast<const uint4*>(src);
+    const uint4 b = *reinterpret_cast<const uint4*>(src + 16);
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+  } else if (avail >= 32 && lo >= xbeg && lo + 36 <= xend) {
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(lo);
+    uint32_t a[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = p[k];
+    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(src) & 3);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = __builtin_amdgcn_alignbyte(a[k + 1], a[k], sh);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (4 * k + b < avail) v |= (uint32_t)src[4 * k + b] << (8 * b);
+      w[k] = v;
+    }
+  }
+  return make_uint4(fp4_of(w[0]) | (fp4_of(w[1]) << 16), fp4_of(w[2]) | (fp4_of(w[3]) << 16),
+                    fp4_of(w[4]) | (fp4_of(w[5]) << 16), fp4_of(w[6]) | (fp4_of(w[7]) << 16));
+}
+
+// One 16-byte chunk of an FP4 conversion: columns [32 c, 32 c + 32) of one
+// row, zeros past n.
+__device__ __forceinline__ void fp4_chunk(const RepackDesc& d, int64_t q) {
+  const int64_t segs = d.ldy >> 4;
+  const int64_t row = q / segs;
+  const int64_t c = q - row * segs;
+  const uint8_t* xend = d.X + (d.m - 1) * d.ldx + d.n;
+  const uint4 o = fp4_pack32(d.X + row * d.ldx + 32 * c, d.n - 32 * c, d.X, xend);
+  *reinterpret_cast<uint4*>(d.Y + row * d.ldy + 16 * c) = o;
 }
 
 // Y[r][c] = X[r][c] for c < n, 0 for n <= c < ldy: a 16-byte aligned copy with
@@ -125,7 +185,11 @@ __global__ __launch_bounds__(256) void k_repack_batch(const RepackDesc* __restri
   }
   const RepackDesc d = descs[lo];
   const int64_t total = d.m * (d.ldy >> 4);
-  for (int64_t q = (b - d.first_block) * 256 + threadIdx.x; q < total; q += d.blocks * 256) repack_chunk(d, q);
+  if (d.fp4) {  // uniform
+    for (int64_t q = (b - d.first_block) * 256 + threadIdx.x; q < total; q += d.blocks * 256) fp4_chunk(d, q);
+  } else {
+    for (int64_t q = (b - d.first_block) * 256 + threadIdx.x; q < total; q += d.blocks * 256) repack_chunk(d, q);
+  }
 }
 
 // Byte -> bit packing (the layout of a packed problem).  0x01 in each
@@ -185,49 +249,23 @@ hipError_t launch_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx,
   return hipGetLastError();
 }
 
-// Byte -> FP4 packing (the layout of the FP4 path): two columns per byte,
-// column 2 c in the low nibble of byte c, the E2M1 code of 1.0 (0b0010) for a
-// nonzero byte and 0 for a zero.  Four input bytes give 16 output bits: bit 7
-// of each nonzero byte (the carry-free test of nibble_of) moves to bit 1 of
-// its nibble.
-__device__ __forceinline__ uint32_t fp4_of(uint32_t d) {
-  const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
-  return ((nz >> 6) & 0x2u) | ((nz >> 10) & 0x20u) | ((nz >> 14) & 0x200u) | ((nz >> 18) & 0x2000u);
-}
-
-// One thread per (row, 32-column group): 16 packed bytes.  Blocks cover 4
-// rows x 64 groups.  Groups that end past n, and unaligned layouts, go byte by
-// byte; bytes of the destination past ceil(n / 2) are not written.
+// One thread per (row, 32-column group): 16 packed bytes (fp4_pack32).
+// Blocks cover 4 rows x 64 groups.  Bytes of the destination past
+// ceil(n / 2) are not written.
 __global__ __launch_bounds__(256) void k_pack_fp4(const uint8_t* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
-                                                  uint8_t* __restrict__ Xq, int64_t ldq, int32_t vec_in,
-                                                  int32_t vec_out) {
+                                                  uint8_t* __restrict__ Xq, int64_t ldq, int32_t vec_out) {
   const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   const int64_t g = (int64_t)blockIdx.y * 64 + threadIdx.x % 64;
   const int64_t nbytes = (n + 1) / 2;  // packed bytes of a row that hold columns
   if (r >= m || 16 * g >= nbytes) return;
-  const uint8_t* xr = X + r * ldx + 32 * g;
+  const uint4 o = fp4_pack32(X + r * ldx + 32 * g, n - 32 * g, X, X + (m - 1) * ldx + n);
   uint8_t* qr = Xq + r * ldq + 16 * g;
-  if (vec_in && 32 * g + 32 <= n) {
-    const uint4 a = *reinterpret_cast<const uint4*>(xr);
-    const uint4 b = *reinterpret_cast<const uint4*>(xr + 16);
-    const uint4 o = make_uint4(fp4_of(a.x) | (fp4_of(a.y) << 16), fp4_of(a.z) | (fp4_of(a.w) << 16),
-                               fp4_of(b.x) | (fp4_of(b.y) << 16), fp4_of(b.z) | (fp4_of(b.w) << 16));
-    if (vec_out) {
-      *reinterpret_cast<uint4*>(qr) = o;
-    } else {
-      const uint32_t w[4] = {o.x, o.y, o.z, o.w};
-#pragma unroll
-      for (int k = 0; k < 16; ++k) qr[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
-    }
-    return;
-  }
-  const int64_t bytes = nbytes - 16 * g < 16 ? nbytes - 16 * g : 16;
-  for (int64_t k = 0; k < bytes; ++k) {
-    const int64_t c = 32 * g + 2 * k;  // columns c and c + 1 of this byte
-    uint32_t v = 0;
-    if (c < n && xr[2 * k] != 0) v |= 0x02u;
-    if (c + 1 < n && xr[2 * k + 1] != 0) v |= 0x20u;
-    qr[k] = (uint8_t)v;
+  if (vec_out && 16 * g + 16 <= nbytes) {
+    *reinterpret_cast<uint4*>(qr) = o;
+  } else {
+    const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+    const int64_t bytes = nbytes - 16 * g < 16 ? nbytes - 16 * g : 16;
+    for (int64_t k = 0; k < bytes; ++k) qr[k] = (uint8_t)(w[k >> 2] >> (8 * (k & 3)));
   }
 }
 
@@ -235,10 +273,9 @@ hipError_t launch_pack_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, 
                            hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const int64_t groups = (n + 31) / 32;
-  const int32_t vec_in = ((uintptr_t)X % 16 == 0 && ldx % 16 == 0) ? 1 : 0;
   const int32_t vec_out = ((uintptr_t)Xq % 16 == 0 && ldq % 16 == 0) ? 1 : 0;
   const dim3 grid((unsigned)((m + 3) / 4), (unsigned)((groups + 63) / 64));
-  hipLaunchKernelGGL(k_pack_fp4, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, vec_in, vec_out);
+  hipLaunchKernelGGL(k_pack_fp4, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, vec_out);
   return hipGetLastError();
 }
 
@@ -259,14 +296,18 @@ hipError_t launch_plain(int cfg, const ProbDev& P, hipStream_t st) {
   return cfg == 1 ? launch_plain_c<Cfg256>(P, st) : launch_plain_c<Cfg128>(P, st);
 }
 
-hipError_t launch_persistent(int cfg, const ProbDev* probs, const UnitRef* units, int nunits, int* head, int grid,
-                             hipStream_t st) {
+hipError_t launch_persistent(int cfg, bool fp4, const ProbDev* probs, const UnitRef* units, int nunits, int* head,
+                             int grid, hipStream_t st) {
   if (nunits <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, head, 0, 1);
-  if (cfg == 1)
-    hipLaunchKernelGGL(k_persistent<Cfg256>, dim3(grid), dim3(Cfg256::NT), 0, st, probs, units, nunits, head);
+  if (cfg == 1 && fp4)
+    hipLaunchKernelGGL((k_persistent<Cfg256, kInFp4>), dim3(grid), dim3(Cfg256::NT), 0, st, probs, units, nunits, head);
+  else if (cfg == 1)
+    hipLaunchKernelGGL((k_persistent<Cfg256, kInBytes>), dim3(grid), dim3(Cfg256::NT), 0, st, probs, units, nunits, head);
+  else if (fp4)
+    hipLaunchKernelGGL((k_persistent<Cfg128, kInFp4>), dim3(grid), dim3(Cfg128::NT), 0, st, probs, units, nunits, head);
   else
-    hipLaunchKernelGGL(k_persistent<Cfg128>, dim3(grid), dim3(Cfg128::NT), 0, st, probs, units, nunits, head);
+    hipLaunchKernelGGL((k_persistent<Cfg128, kInBytes>), dim3(grid), dim3(Cfg128::NT), 0, st, probs, units, nunits, head);
   return hipGetLastError();
 }
 
@@ -315,11 +356,15 @@ int occupancy(int cfg) {
   return blocks;
 }
 
-int persistent_occupancy(int cfg) {
+int persistent_occupancy(int cfg, bool fp4) {
   int blocks = 0;
-  hipError_t e = cfg == 1
-                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg256>, Cfg256::NT, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg128>, Cfg128::NT, 0);
+  hipError_t e;
+  if (cfg == 1)
+    e = fp4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg256, kInFp4>, Cfg256::NT, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg256, kInBytes>, Cfg256::NT, 0);
+  else
+    e = fp4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg128, kInFp4>, Cfg128::NT, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_persistent<Cfg128, kInBytes>, Cfg128::NT, 0);
   if (e != hipSuccess || blocks < 1) blocks = 1;
   return blocks;
 }

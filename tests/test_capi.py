@@ -219,7 +219,7 @@ def test_packed_argument_checks(L):
 def test_fp4_argument_checks(L):
     """FP4 input (2 columns per byte) and the Gram choice: pitch in bytes of 2
     columns and at most 2^23, no validate, no sparse algorithm, no int8 Gram;
-    bit input takes no FP4 Gram; batches run the FP4 Gram on FP4 input only;
+    bit input takes no FP4 Gram; batches check each problem the same way;
     the packing utility checks its pitches."""
     from paper_2411_19702_amd import mi
     def prob(**kw):
@@ -238,10 +238,8 @@ def test_fp4_argument_checks(L):
     assert ex(packed=mi.MI_INPUT_BITS, ldx=3, gram=mi.MI_GRAM_FP4) == 1
     assert ex(packed=mi.MI_INPUT_BYTES, ldx=17, gram=mi.MI_GRAM_FP4, algo=mi.MI_ALGO_SPARSE) == 1
     for mode in (mi.MI_BATCH_PERSISTENT, mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL):
-        arr = (mi.mi_problem * 1)(prob(packed=mi.MI_INPUT_BYTES, ldx=17, gram=mi.MI_GRAM_FP4))
-        assert L.mi_all_pairs_batched(arr, 1, None, mode) == 1    # conversion is not done in batches
-    arr = (mi.mi_problem * 1)(prob())
-    assert L.mi_all_pairs_batched(arr, 1, None, mi.MI_BATCH_PERSISTENT) == 1
+        arr = (mi.mi_problem * 1)(prob(gram=mi.MI_GRAM_INT8))
+        assert L.mi_all_pairs_batched(arr, 1, None, mode) == 1    # checked per problem in batches too
     assert L.mi_pack_fp4(16, 10, 17, 16, 32, 9, None) == 1     # ldx < n
     assert L.mi_pack_fp4(16, 10, 17, 17, 32, 8, None) == 1     # ldq < ceil(n / 2)
     assert L.mi_pack_fp4(None, 10, 17, 17, 32, 9, None) == 1

@@ -143,9 +143,9 @@ def test_fp4_units_stay_below_2_24_rows():
     assert int(cs.max()) > (1 << 24), "the case must hold counts above 2^24"
 
 
-@pytest.mark.parametrize("mode", [mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL])
+@pytest.mark.parametrize("mode", [mi.MI_BATCH_PERSISTENT, mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL])
 def test_fp4_input_in_batches(mode):
-    """FP4 and byte problems in one graph / sequential batch: each equal to its single call."""
+    """FP4 and byte problems in one batch (every mode): each equal to its single int8 call."""
     say(f"[fp4] batch mode {mode}")
     specs = [synth.spec_random(950 + k, 2000 + 900 * k, 70 + 53 * k, 0.0, 0.8, planted=3) for k in range(4)]
     Xs = [synth.generate(s, device=DEV) for s in specs]
@@ -167,6 +167,39 @@ def test_fp4_input_in_batches(mode):
             mi.mi_all_pairs_ex(X, out=want, gram=mi.MI_GRAM_INT8)
             torch.cuda.synchronize()
             assert torch.equal(o, want)
+
+
+@pytest.mark.parametrize("mode", [mi.MI_BATCH_PERSISTENT, mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL])
+def test_fp4_gram_on_bytes_in_batches(mode):
+    """Byte problems converted to FP4 inside a batch (aligned, pitched and
+    unaligned, mixed with int8 ones and with the library's choice; the
+    persistent mode runs one launch per Gram): each bitwise equal to its
+    single int8 call, over two calls (the graph mode replays its graph)."""
+    say(f"[fp4] byte problems with the FP4 Gram, batch mode {mode}")
+    shapes = [(3000, 200, None), (20000, 1700, None), (5000, 333, 341), (777, 129, None), (40000, 1600, None),
+              (100, 40, 45)]
+    Xs, specs = [], []
+    for k, (m, n, pitch) in enumerate(shapes):
+        spec = synth.spec_random(980 + k, m, n, 0.0, 0.8, planted=2, ldx=pitch)
+        X = synth.generate(spec, device=DEV)[:, :n]
+        if k == 2:  # base off by one byte: unaligned
+            W = torch.zeros((m, n + 9), dtype=torch.uint8, device=DEV)
+            W[:, 1:1 + n].copy_(X)
+            X = W[:, 1:1 + n]
+        Xs.append(X)
+        specs.append(spec)
+    grams = [mi.MI_GRAM_FP4, mi.MI_GRAM_AUTO, mi.MI_GRAM_FP4, mi.MI_GRAM_INT8, mi.MI_GRAM_FP4, mi.MI_GRAM_FP4]
+    outs = [torch.full((s.n, s.n), float("nan"), device=DEV) for s in specs]
+    n11s = [torch.full((s.n, s.n), -1, dtype=torch.int32, device=DEV) for s in specs]
+    probs = [mi.make_problem(X, o, n11_out=c, gram=g) for X, o, c, g in zip(Xs, outs, n11s, grams)]
+    for _ in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        mi.mi_all_pairs_batched(probs, mode=mode)
+        torch.cuda.synchronize()
+        for X, o, c in zip(Xs, outs, n11s):
+            want, wc = _run(X, X.shape[1], gram=mi.MI_GRAM_INT8)[:2]
+            assert torch.equal(o, want) and torch.equal(c, wc)
 
 
 def test_fp4_rejected_where_unsupported():
