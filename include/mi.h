@@ -149,12 +149,12 @@ typedef struct mi_problem {
    * ceil(n / 2), at most 2^23; validate must be 0.  Results are the same as
    * for the byte layout.  Packed layouts take the dense algorithm only; bits
    * in single calls and the graph / sequential batch modes, FP4 in single
-   * calls and every batch mode; the server takes neither. */
+   * calls and every batch mode; the server takes the byte layout only. */
   int32_t packed;
   /* mi_gram.  MI_GRAM_FP4 needs byte or FP4 input; MI_GRAM_INT8 byte or bit
-   * input.  Batches follow each problem's choice (byte input converted in
-   * the batch's scratch).  The server runs the int8 Gram and rejects
-   * MI_GRAM_FP4 (its HBM budget holds no conversion buffer). */
+   * input.  Batches and the server follow each problem's choice (byte input
+   * converted in library scratch; the server charges that buffer to the
+   * request's HBM budget). */
   int32_t gram;
 } mi_problem;
 

@@ -25,8 +25,10 @@
  * batch (counts are exact integers and MI is a pure function of them).
  *
  * Memory charged to a request: X (m * ldx bytes), out (4 n^2), the optional
- * outputs, and the library scratch it needs (split-K workspace, a repacked
- * copy of X when its layout is not 16-byte aligned).
+ * outputs, and the library scratch it needs (split-K workspace; the FP4 copy
+ * of X, m * ceil(n / 2) bytes with the pitch rounded up to 16, when the
+ * request runs the FP4 Gram (mi_problem.gram); otherwise a repacked copy of X
+ * when its layout is not 16-byte aligned).  Requests take the byte layout.
  *
  * Thread safety: submit, poll and wait may be called from any thread.  The
  * caller keeps X and the outputs alive until the ticket has completed.

@@ -111,7 +111,10 @@ size_t request_bytes(const mi_problem& p, int64_t ldx) {
     const int cfg = p.tile == MI_TILE_256 ? 1 : 0;
     mi::Plan pl = mi::make_plan(p.m, p.n, p.tile == 0 ? (p.n >= 1536 ? 1 : 0) : cfg, 2);
     b += mi::workspace_bytes(pl);  // the most any plan of this shape uses
-    if (!mi::is_aligned(p.X, ldx)) b += (size_t)p.m * (size_t)mi::packed_pitch(p.n);
+    if (mi::converts_to_fp4(&p))    // the FP4 copy of X (an unaligned X needs no repack then)
+      b += (size_t)p.m * (size_t)mi::packed_pitch((p.n + 1) / 2);
+    else if (!mi::is_aligned(p.X, ldx))
+      b += (size_t)p.m * (size_t)mi::packed_pitch(p.n);
   }
   return b;
 }
@@ -337,10 +340,8 @@ mi_status mi_server_submit(mi_server* s, const mi_problem* p, uint64_t* ticket) 
   if (p->validate) return mi::fail(MI_ERR_INVALID_ARG, "validate is not supported by the server");
   if (p->algo != MI_ALGO_DENSE) return mi::fail(MI_ERR_INVALID_ARG, "the server takes only the dense algorithm");
   if (p->packed) return mi::fail(MI_ERR_INVALID_ARG, "the server takes only the byte layout");
-  if (p->gram == MI_GRAM_FP4) return mi::fail(MI_ERR_INVALID_ARG, "the server runs the int8 Gram");
   Req r;
   r.p = *p;
-  r.p.gram = MI_GRAM_INT8;  // no conversion scratch outside the admitted budget
   r.bytes = request_bytes(*p, ldx);
   r.est_us = estimate_us(*p);
   r.t_submit = Clock::now();

@@ -211,4 +211,24 @@ def test_fp4_rejected_where_unsupported():
         mi.mi_all_pairs_ex(mi.mi_pack_fp4(X), out=out, n=40, packed=mi.MI_INPUT_FP4, validate=True)
     with mi.Server(hbm_budget_bytes=1 << 30) as srv:
         with pytest.raises(mi.MIError):
-            srv.submit(X, out, gram=mi.MI_GRAM_FP4)
+            srv.submit(mi.mi_pack_fp4(X), out, n=40, packed=mi.MI_INPUT_FP4)
+
+
+def test_fp4_in_server():
+    """Requests on the FP4 Gram (the library's choice and forced) next to
+    int8 ones in the server: each bitwise equal to its single int8 call."""
+    say("[fp4] server requests")
+    shapes = [(30000, 1700, mi.MI_GRAM_AUTO), (4000, 300, mi.MI_GRAM_FP4), (20000, 2000, mi.MI_GRAM_INT8),
+              (9000, 777, mi.MI_GRAM_FP4), (100, 50, mi.MI_GRAM_AUTO)]
+    Xs = [synth.generate(synth.spec_random(990 + k, m, n, 0.0, 0.6, planted=2), device=DEV)
+          for k, (m, n, _) in enumerate(shapes)]
+    outs = [torch.full((n, n), float("nan"), device=DEV) for (_, n, _) in shapes]
+    with mi.Server(hbm_budget_bytes=8 << 30, max_slots=3) as srv:
+        tickets = [srv.submit(X, o, gram=g) for X, o, (_, _, g) in zip(Xs, outs, shapes)]
+        for t in tickets:
+            srv.wait(t)
+    for X, o in zip(Xs, outs):
+        want = torch.empty_like(o)
+        mi.mi_all_pairs_ex(X, out=want, gram=mi.MI_GRAM_INT8)
+        torch.cuda.synchronize()
+        assert torch.equal(o, want)
