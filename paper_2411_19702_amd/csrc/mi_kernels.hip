@@ -37,9 +37,11 @@ __global__ __launch_bounds__(C::NT) void k_plain(ProbDev P) {
 
 // Persistent workgroups pull units of many datasets from a device queue.  IN:
 // the input layout of every dataset of the launch (bytes: int8 Gram, FP4: FP4
-// Gram); a batch with both runs one launch of each.
+// Gram); a batch with both runs one launch of each.  Two waves per SIMD are
+// requested explicitly: left alone, the compiler gives the 128-wide FP4
+// variant 211 VGPRs + 64 AGPRs and a single wave per SIMD.
 template <class C, int IN>
-__global__ __launch_bounds__(C::NT) void k_persistent(const ProbDev* __restrict__ probs,
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_persistent(const ProbDev* __restrict__ probs,
                                                       const UnitRef* __restrict__ units, int nunits,
                                                       int* __restrict__ head) {
   MI_DECLARE_SMEM(C, sm);

@@ -169,13 +169,14 @@ def test_fp4_input_in_batches(mode):
             assert torch.equal(o, want)
 
 
+@pytest.mark.parametrize("tile", [mi.MI_TILE_AUTO, mi.MI_TILE_128])
 @pytest.mark.parametrize("mode", [mi.MI_BATCH_PERSISTENT, mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL])
-def test_fp4_gram_on_bytes_in_batches(mode):
+def test_fp4_gram_on_bytes_in_batches(mode, tile):
     """Byte problems converted to FP4 inside a batch (aligned, pitched and
     unaligned, mixed with int8 ones and with the library's choice; the
     persistent mode runs one launch per Gram): each bitwise equal to its
     single int8 call, over two calls (the graph mode replays its graph)."""
-    say(f"[fp4] byte problems with the FP4 Gram, batch mode {mode}")
+    say(f"[fp4] byte problems with the FP4 Gram, batch mode {mode}, tile {tile}")
     shapes = [(3000, 200, None), (20000, 1700, None), (5000, 333, 341), (777, 129, None), (40000, 1600, None),
               (100, 40, 45)]
     Xs, specs = [], []
@@ -191,7 +192,7 @@ def test_fp4_gram_on_bytes_in_batches(mode):
     grams = [mi.MI_GRAM_FP4, mi.MI_GRAM_AUTO, mi.MI_GRAM_FP4, mi.MI_GRAM_INT8, mi.MI_GRAM_FP4, mi.MI_GRAM_FP4]
     outs = [torch.full((s.n, s.n), float("nan"), device=DEV) for s in specs]
     n11s = [torch.full((s.n, s.n), -1, dtype=torch.int32, device=DEV) for s in specs]
-    probs = [mi.make_problem(X, o, n11_out=c, gram=g) for X, o, c, g in zip(Xs, outs, n11s, grams)]
+    probs = [mi.make_problem(X, o, n11_out=c, gram=g, tile=tile) for X, o, c, g in zip(Xs, outs, n11s, grams)]
     for _ in range(2):
         for o in outs:
             o.fill_(float("nan"))
