@@ -203,6 +203,30 @@ def test_fp4_gram_on_bytes_in_batches(mode, tile):
             assert torch.equal(o, want) and torch.equal(c, wc)
 
 
+def test_fp4_validate_and_plan_ex():
+    """validate checks the bytes before the FP4 conversion; mi_plan_ex reports
+    the Gram each call runs (FP4 from n >= 1536 and m n^2 >= 6e10)."""
+    X = (torch.rand((3000, 1600), device=DEV) < 0.3).to(torch.uint8)
+    out = mi.mi_all_pairs_ex(X, validate=True, gram=mi.MI_GRAM_FP4)
+    want = mi.mi_all_pairs_ex(X, gram=mi.MI_GRAM_INT8)
+    torch.cuda.synchronize()
+    assert torch.equal(out, want)
+    X[1234, 777] = 2
+    with pytest.raises(mi.MIError) as ei:
+        mi.mi_all_pairs_ex(X, validate=True, gram=mi.MI_GRAM_FP4)
+    assert ei.value.status == 2                      # MI_ERR_NOT_BINARY
+    big = torch.zeros((40000, 2048), dtype=torch.uint8, device=DEV)
+    assert mi.mi_plan_ex(big)[2] == mi.MI_GRAM_FP4       # 1.7e11 >= 6e10
+    assert mi.mi_plan_ex(big[:5000])[2] == mi.MI_GRAM_INT8  # 2.1e10
+    assert mi.mi_plan_ex(big[:, :1024])[2] == mi.MI_GRAM_INT8
+    assert mi.mi_plan_ex(big, gram=mi.MI_GRAM_INT8)[2] == mi.MI_GRAM_INT8
+    assert mi.mi_plan_ex(big[:5000], gram=mi.MI_GRAM_FP4)[2] == mi.MI_GRAM_FP4
+    Q = mi.mi_pack_fp4(big[:100])
+    assert mi.mi_plan_ex(Q, n=2048, packed=mi.MI_INPUT_FP4)[2] == mi.MI_GRAM_FP4
+    tile, splits, _ = mi.mi_plan_ex(big)
+    assert tile in (mi.MI_TILE_128, mi.MI_TILE_256) and splits >= 1
+
+
 def test_fp4_rejected_where_unsupported():
     X = torch.zeros((10, 40), dtype=torch.uint8, device=DEV)
     out = torch.empty((40, 40), device=DEV)
