@@ -101,12 +101,39 @@ def cpu_baseline(spec, target_s: float):
     k2 = int(max(6, min(spec.n, (2 * target_s / max(per_pair, 1e-9)) ** 0.5)))
     dt, k = run(k2)
     pu = m * k * (k + 1) / 2
+    # One thread: pairs one call at a time (each call's parallel loop has a
+    # single iteration), about 2 s of them; only where a pair's rows outweigh
+    # the per-call overhead.
+    single = None
+    if m >= 100_000:
+        cols = [int(c) for c in rng.choice(spec.n, size=32, replace=False)]
+        Xs = synth.columns(spec, sorted(cols)).numpy()
+        t0 = time.perf_counter()
+        oracle.pairs(Xs, [0], [1])
+        per = max(time.perf_counter() - t0, 1e-6)
+        npairs = int(max(4, min(496, 2.0 / per)))
+        ij = [(a, b) for a in range(32) for b in range(a, 32)][:npairs]
+        t0 = time.perf_counter()
+        for a, b in ij:
+            oracle.pairs(Xs, [a], [b])
+        dt1 = time.perf_counter() - t0
+        single = (len(ij) * m / dt1, f"{len(ij)} pairs, one call each, of 32 random columns x all {m} rows; {dt1:.2f} s")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": pu / dt,
         "unit": "pair-updates/s",
         "cores": oracle.threads(),
         "kind": "oracle",
         "sample": f"all {k * (k + 1) // 2} pairs (i <= j) of {k} random columns x all {m} rows of the same matrix; {dt:.2f} s",
+        "single_thread_value": single[0] if single else None,
+        "single_thread_sample": single[1] if single else None,
+        "cpu_model": model,
+        "nproc": os.cpu_count(),
     }
 
 
