@@ -93,31 +93,29 @@ def cpu_baseline(spec, target_s: float):
         Xs = synth.columns(spec, cols).numpy()
         t0 = time.perf_counter()
         oracle.all_pairs(Xs)
-        return time.perf_counter() - t0, ncols
+        return time.perf_counter() - t0, ncols, Xs
 
-    dt, k = run(6)
+    dt, k, _ = run(6)
     # pairs scale as k(k+1)/2: pick k for about target_s seconds
     per_pair = dt / (k * (k + 1) / 2)
     k2 = int(max(6, min(spec.n, (2 * target_s / max(per_pair, 1e-9)) ** 0.5)))
-    dt, k = run(k2)
+    dt, k, Xs = run(k2)
     pu = m * k * (k + 1) / 2
-    # One thread: pairs one call at a time (each call's parallel loop has a
-    # single iteration), about 2 s of them; only where a pair's rows outweigh
-    # the per-call overhead.
+    # One thread: pairs of the same sampled matrix, one call at a time (each
+    # call's parallel loop has a single iteration), about 2 s of them; only
+    # where a pair's rows outweigh the per-call overhead.
     single = None
     if m >= 100_000:
-        cols = [int(c) for c in rng.choice(spec.n, size=32, replace=False)]
-        Xs = synth.columns(spec, sorted(cols)).numpy()
         t0 = time.perf_counter()
         oracle.pairs(Xs, [0], [1])
         per = max(time.perf_counter() - t0, 1e-6)
-        npairs = int(max(4, min(496, 2.0 / per)))
-        ij = [(a, b) for a in range(32) for b in range(a, 32)][:npairs]
+        npairs = int(max(4, min(k * (k + 1) // 2, 2.0 / per)))
+        ij = [(int(a), int(b)) for a, b in zip(rng.integers(0, k, size=npairs), rng.integers(0, k, size=npairs))]
         t0 = time.perf_counter()
         for a, b in ij:
-            oracle.pairs(Xs, [a], [b])
+            oracle.pairs(Xs, [min(a, b)], [max(a, b)])
         dt1 = time.perf_counter() - t0
-        single = (len(ij) * m / dt1, f"{len(ij)} pairs, one call each, of 32 random columns x all {m} rows; {dt1:.2f} s")
+        single = (len(ij) * m / dt1, f"{len(ij)} random pairs of the same {k}-column sample, one call each; {dt1:.2f} s")
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
