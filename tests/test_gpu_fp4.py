@@ -65,7 +65,7 @@ CASES = [  # (m, n): one and several 128-row stages, ragged rows and columns, se
 
 
 @pytest.mark.parametrize("m,n", CASES)
-@pytest.mark.parametrize("epi", [0, 2])
+@pytest.mark.parametrize("epi", [0, 1, 2])
 def test_fp4_gram_equals_int8(m, n, epi):
     say(f"[fp4] {m}x{n} epi={epi}")
     spec = synth.spec_random(11 * m + n, m, n, 0.0, 1.0, planted=max(1, n // 20))
@@ -78,6 +78,23 @@ def test_fp4_gram_equals_int8(m, n, epi):
     _same(b, q, "FP4 input")
     if m * n <= 1_000_000:
         compare_full(X.cpu().numpy(), n, f[0].cpu().numpy(), f[1].cpu().numpy(), f[2].cpu().numpy()[:n])
+
+
+def test_fp4_sparse_pairs_output():
+    """The threshold pair list on the FP4 Gram: the same set of (i, j, MI) as
+    on the int8 Gram (append order is unspecified), and the same exact count."""
+    say("[fp4] sparse pairs output")
+    spec = synth.spec_random(77, 20000, 1700, 0.0, 0.6, planted=40)
+    X = synth.generate(spec, device=DEV)
+    res = []
+    for g in (mi.MI_GRAM_INT8, mi.MI_GRAM_FP4):
+        pairs, count = mi.mi_all_pairs_threshold(X, threshold=0.02, capacity=1 << 16, gram=g)
+        torch.cuda.synchronize()
+        k = int(count.item())
+        assert 0 < k <= (1 << 16)
+        rows = pairs[:k].cpu().numpy()
+        res.append((k, set(map(tuple, rows.tolist()))))
+    assert res[0][0] == res[1][0] and res[0][1] == res[1][1]
 
 
 @pytest.mark.parametrize("tile,splits", [(1, 1), (2, 1), (1, 5), (2, 3), (2, 7)])
