@@ -272,10 +272,13 @@ mi_status mi_plan_ex(const mi_problem* p, int32_t* tile, int32_t* splits, int32_
 mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits);
 
 /* Autotuner: time the candidate (tile, splits) configurations for this shape
- * on the current device (on a scratch all-ones matrix: every split-K partial
- * is then published, the costly case) and remember the fastest for every
- * later call with the same shape class.  *best_ms receives its time (may be
- * NULL). */
+ * on the current device, with the Gram the library would run for byte input
+ * of this shape (FP4 from n >= 1536 and m n^2 >= 6e10, else int8), on a
+ * scratch all-ones matrix in that layout (every split-K partial is then
+ * published, the costly case), and remember the fastest for every later call
+ * with the same shape class and Gram.  *best_ms receives its time (may be
+ * NULL).  The tuner file holds one JSON line per entry; lines without the
+ * "fp4" field are int8 entries. */
 mi_status mi_tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms);
 mi_status mi_tuner_save(const char* path);   /* JSON lines */
 mi_status mi_tuner_load(const char* path);

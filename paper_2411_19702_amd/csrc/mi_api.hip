@@ -229,10 +229,13 @@ static int heuristic_splits(int64_t m, const Plan& p1, int cus, double rows_per_
 static int heuristic_cfg(int64_t m, int64_t n) { return (n >= 1536 && m >= 16384) ? 1 : 0; }
 
 // Tuned entries, keyed by a shape class: m in quarter octaves, n in 64-column
-// steps, and whether the fast aligned load path applies.
+// steps, whether the fast aligned load path applies, and the Gram (FP4
+// entries time the converted, always aligned, layout).
 struct ShapeKey {
-  int mb, nb, aligned;
-  bool operator<(const ShapeKey& o) const { return std::tie(mb, nb, aligned) < std::tie(o.mb, o.nb, o.aligned); }
+  int mb, nb, aligned, fp4;
+  bool operator<(const ShapeKey& o) const {
+    return std::tie(mb, nb, aligned, fp4) < std::tie(o.mb, o.nb, o.aligned, o.fp4);
+  }
 };
 struct Tuned {
   int cfg, splits;
@@ -241,11 +244,12 @@ struct Tuned {
 static std::mutex g_tune_mu;
 static std::map<ShapeKey, Tuned> g_tuned;
 
-static ShapeKey shape_key(int64_t m, int64_t n, bool aligned) {
+static ShapeKey shape_key(int64_t m, int64_t n, bool aligned, bool fp4) {
   ShapeKey k;
   k.mb = (int)std::lround(4.0 * std::log2((double)std::max<int64_t>(m, 1)));
   k.nb = (int)cdiv(n, 64);
-  k.aligned = aligned ? 1 : 0;
+  k.aligned = (aligned || fp4) ? 1 : 0;
+  k.fp4 = fp4 ? 1 : 0;
   return k;
 }
 
@@ -255,9 +259,9 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
   if (s != MI_OK) return s;
   int cfg = tile_req == MI_TILE_256 ? 1 : (tile_req == MI_TILE_128 ? 0 : -1);
   int splits = splits_req;
-  if (splits <= 0 && !fp4) {  // tuned entries time the int8 Gram
+  if (splits <= 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(shape_key(m, n, aligned));
+    auto it = g_tuned.find(shape_key(m, n, aligned, fp4));
     if (it != g_tuned.end() && (cfg < 0 || cfg == it->second.cfg)) {
       cfg = it->second.cfg;
       splits = it->second.splits;
@@ -797,12 +801,14 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   DeviceInfo di;
   mi_status s = device_info(&di);
   if (s != MI_OK) return s;
-  // Unaligned layouts are repacked to a packed pitch first, so time on a
-  // matrix of that pitch.  It is all ones: every count is nonzero, so every
-  // split-K partial is published (the kernels skip zero partials), which is
-  // the costly case.
+  // The Gram the library would run for byte input of this shape.  Unaligned
+  // layouts are repacked (int8) or converted (FP4) to a 16-byte pitch first,
+  // so time on a matrix of that pitch.  It is all ones (bytes 1, or FP4
+  // codes 0b0010 in every nibble): every count is nonzero, so every split-K
+  // partial is published (the kernels skip zero partials), the costly case.
+  const bool fp4 = fp4_preferred(m, n);
   const bool aligned = ldx % 16 == 0;
-  const int64_t ld = aligned ? ldx : packed_pitch(n);
+  const int64_t ld = fp4 ? packed_pitch((n + 1) / 2) : (aligned ? ldx : packed_pitch(n));
   uint8_t* X = nullptr;
   float* out = nullptr;
   const size_t xbytes = (size_t)m * (size_t)ld;
@@ -819,7 +825,7 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   hipEvent_t e0 = nullptr, e1 = nullptr;
   Tuned best{-1, 0, 1e30};
   auto body = [&]() -> mi_status {
-    HIPCHK(hipMemset(X, 1, xbytes));
+    HIPCHK(hipMemset(X, fp4 ? 0x22 : 1, xbytes));
     HIPCHK(hipStreamCreate(&st));
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -829,7 +835,7 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
       std::vector<int> cands;
       for (int sp = 1; sp <= 16; ++sp) cands.push_back(sp);
       for (int sp : {20, 24, 32, 48, 64, 96, 128, 192, 256}) cands.push_back(sp);
-      cands.push_back(heuristic_splits(m, p1, di.cus));
+      cands.push_back(heuristic_splits(m, p1, di.cus, fp4 ? 2.0 : 1.0));
       std::sort(cands.begin(), cands.end());
       cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
       const int32_t* tiles = tile_table(p1.ntp, &te);
@@ -838,12 +844,14 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
         if (sp > p1.ksteps) continue;
         const Plan pl = make_plan(m, n, cfg, sp);
         if (pl.splits != sp || (double)pl.ntiles * pl.splits > 4.0e6) continue;
+        if (fp4 && pl.kchunk > kFp4MaxUnitRows) continue;  // FP32 counts exact per unit
         void* ws = nullptr;
         mi_status ss = workspace(st, 0, workspace_bytes(pl), &ws);
         if (ss != MI_OK) return ss;
         mi_problem pr;
         mi_problem_init(&pr, X, m, n, out);
         pr.ldx = ld;
+        pr.packed = fp4 ? MI_INPUT_FP4 : MI_INPUT_BYTES;
         const ProbDev P = make_probdev(&pr, X, ld, pl, ws, tiles);
         HIPCHK(launch_plain(cfg, P, st));  // warm-up
         float best_here = 1e30f;
@@ -875,7 +883,7 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   if (best.cfg < 0) return fail(MI_ERR_DEVICE, "tuner found no runnable configuration");
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[shape_key(m, n, aligned)] = best;
+    g_tuned[shape_key(m, n, aligned, fp4)] = best;
   }
   if (tile) *tile = best.cfg == 1 ? MI_TILE_256 : MI_TILE_128;
   if (splits) *splits = best.splits;
@@ -889,8 +897,9 @@ mi_status tuner_save(const char* path) {
   if (!f) return fail(MI_ERR_INVALID_ARG, "cannot open %s for writing", path);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& kv : g_tuned)
-    fprintf(f, "{\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %.6f}\n", kv.first.mb,
-            kv.first.nb, kv.first.aligned, cfg_tile(kv.second.cfg), kv.second.splits, kv.second.ms);
+    fprintf(f, "{\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %.6f, \"fp4\": %d}\n",
+            kv.first.mb, kv.first.nb, kv.first.aligned, cfg_tile(kv.second.cfg), kv.second.splits, kv.second.ms,
+            kv.first.fp4);
   fclose(f);
   return MI_OK;
 }
@@ -906,9 +915,10 @@ mi_status tuner_load(const char* path) {
     ShapeKey k;
     Tuned t;
     int tile = 0;
-    if (sscanf(line, " {\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %lf}", &k.mb,
-               &k.nb, &k.aligned, &tile, &t.splits, &t.ms) == 6 &&
-        (tile == 128 || tile == 256) && t.splits >= 1) {
+    k.fp4 = 0;  // entries without the field time the int8 Gram
+    const int got = sscanf(line, " {\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %lf, \"fp4\": %d}",
+                           &k.mb, &k.nb, &k.aligned, &tile, &t.splits, &t.ms, &k.fp4);
+    if (got >= 6 && (tile == 128 || tile == 256) && t.splits >= 1 && (k.fp4 == 0 || k.fp4 == 1)) {
       t.cfg = tile == 256 ? 1 : 0;
       g_tuned[k] = t;
       ++nread;
@@ -1040,6 +1050,6 @@ void mi_tuner_clear(void) { tuner_clear(); }
 
 const char* mi_last_error(void) { return last_error(); }
 
-const char* mi_version(void) { return "mi355x-binary-mi 0.1 (gfx950, int8 MFMA)"; }
+const char* mi_version(void) { return "mi355x-binary-mi 0.2 (gfx950, int8 and FP4 MFMA)"; }
 
 }  // extern "C"

@@ -106,12 +106,17 @@ def test_plan_and_tuner_argument_checks(L, tmp_path):
     f = tmp_path / "tuned.jsonl"
     assert L.mi_tuner_save(str(f).encode()) == 0
     f.write_text('{"mb": 40, "nb": 16, "aligned": 1, "tile": 128, "splits": 7, "ms": 1.5}\nnot json\n'
-                 '{"mb": 41, "nb": 16, "aligned": 1, "tile": 96, "splits": 7, "ms": 1.5}\n')
+                 '{"mb": 41, "nb": 16, "aligned": 1, "tile": 96, "splits": 7, "ms": 1.5}\n'
+                 '{"mb": 80, "nb": 64, "aligned": 1, "tile": 256, "splits": 9, "ms": 3.2, "fp4": 1}\n'
+                 '{"mb": 81, "nb": 64, "aligned": 1, "tile": 256, "splits": 9, "ms": 3.2, "fp4": 7}\n')
     assert L.mi_tuner_load(str(f).encode()) == 0
     out = tmp_path / "again.jsonl"
     assert L.mi_tuner_save(str(out).encode()) == 0
     text = out.read_text()
-    assert '"splits": 7' in text and '"tile": 96' not in text and text.count("\n") == 1
+    lines = text.strip().split("\n")
+    assert len(lines) == 2 and '"tile": 96' not in text and '"fp4": 7' not in text
+    assert any('"splits": 7' in ln and '"fp4": 0' in ln for ln in lines)      # an entry without the field: int8
+    assert any('"splits": 9' in ln and '"fp4": 1' in ln for ln in lines)
     L.mi_tuner_clear()
 
 
