@@ -299,10 +299,10 @@ def bench_categorical(dev, reps: int = 5):
 
 def bench_packed(dev, reps: int = 10):
     """Packed inputs on the 1,000,000 x 4,096 workload: the int8 byte kernel;
-    bit-packed input (8x fewer input bytes, int8 Gram) and its packing pass;
-    FP4 input (2x fewer bytes, FP4 Gram) and its packing pass; the byte call
-    with the FP4 Gram (conversion included).  Timed with HIP events on the
-    stream."""
+    bit-packed input (8x fewer input bytes) on the int8 Gram and on the FP4
+    Gram (the library's choice), and its packing pass; FP4 input (2x fewer
+    bytes, FP4 Gram) and its packing pass; the byte call with the FP4 Gram
+    (conversion included).  Timed with HIP events on the stream."""
     import torch
     from paper_2411_19702_amd import mi, synth
     spec = synth.spec_large()
@@ -325,7 +325,8 @@ def bench_packed(dev, reps: int = 10):
 
     Q = mi.mi_pack_fp4(X)
     t_bytes = timed(lambda: mi.mi_all_pairs_ex(X, out=out, gram=mi.MI_GRAM_INT8))
-    t_packed = timed(lambda: mi.mi_all_pairs_ex(P, out=out, n=n, packed=True))
+    t_packed = timed(lambda: mi.mi_all_pairs_ex(P, out=out, n=n, packed=True, gram=mi.MI_GRAM_INT8))
+    t_packed4 = timed(lambda: mi.mi_all_pairs_ex(P, out=out, n=n, packed=True))
     t_pack = timed(lambda: mi.mi_pack_bits(X, out=P))
     t_fp4 = timed(lambda: mi.mi_all_pairs_ex(Q, out=out, n=n, packed=mi.MI_INPUT_FP4))
     t_pack4 = timed(lambda: mi.mi_pack_fp4(X, out=Q))
@@ -335,6 +336,8 @@ def bench_packed(dev, reps: int = 10):
            "pack_then_packed_ms": t_pack + t_packed, "input_bytes": spec.m * n, "packed_input_bytes": P.numel(),
            "packed_pair_updates_per_s": pu / (t_packed * 1e-3),
            "packed_int8_frac": 2 * pu / (t_packed * 1e-3) / PEAK_INT8_OPS,
+           "packed_fp4_gram_ms": t_packed4, "packed_fp4_gram_pair_updates_per_s": pu / (t_packed4 * 1e-3),
+           "packed_fp4_gram_frac": 2 * pu / (t_packed4 * 1e-3) / PEAK_FP4_OPS,
            "fp4_input_ms": t_fp4, "fp4_pack_pass_ms": t_pack4, "fp4_input_bytes": Q.numel(),
            "bytes_fp4_gram_ms": t_bytes_fp4, "fp4_pair_updates_per_s": pu / (t_fp4 * 1e-3),
            "fp4_frac": 2 * pu / (t_fp4 * 1e-3) / PEAK_FP4_OPS}

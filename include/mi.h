@@ -101,8 +101,9 @@ typedef enum mi_input {
 typedef enum mi_gram {
   MI_GRAM_AUTO = 0,  /* the library's choice: FP4 for byte input with n >= 1536 and       */
                      /* m n^2 >= 6e10 (converted to the FP4 layout first, in scratch     */
-                     /* memory of half the input's size), int8 otherwise                 */
-  MI_GRAM_INT8 = 1,  /* v_mfma_i32_32x32x32_i8 on bytes (or unpacked bits)                */
+                     /* memory of half the input's size), for bit input with n >= 512    */
+                     /* (unpacked on chip to FP4 codes), for FP4 input; int8 otherwise   */
+  MI_GRAM_INT8 = 1,  /* v_mfma_i32_32x32x32_i8 on bytes (or bits unpacked to bytes)       */
   MI_GRAM_FP4 = 2    /* v_mfma_scale_f32_32x32x64_f8f6f4 on E2M1 codes: twice the samples */
                      /* per byte staged and ~1.7x the int8 instruction rate               */
 } mi_gram;
@@ -142,8 +143,9 @@ typedef struct mi_problem {
   /* Input layout (mi_input).  MI_INPUT_BITS: X holds 8 columns per byte, bit
    * k (least significant first) of byte b of a row being column 8 b + k; ldx
    * is then the row pitch in bytes, >= ceil(n / 8) (0 means ceil(n / 8)).  The
-   * kernel reads an eighth of the bytes and unpacks them on chip; validate is
-   * a no-op (every bit is 0 or 1).  MI_INPUT_FP4: X holds 2 columns per byte,
+   * kernel reads an eighth of the bytes and unpacks them on chip (to bytes
+   * for the int8 Gram, to FP4 codes for the FP4 Gram); validate is a no-op
+   * (every bit is 0 or 1).  MI_INPUT_FP4: X holds 2 columns per byte,
    * column 2 c in the low nibble of byte c, each nibble 0b0010 (a one) or 0
    * (as mi_pack_fp4 writes them; other codes give undefined counts); ldx >=
    * ceil(n / 2), at most 2^23; validate must be 0.  Results are the same as
@@ -151,8 +153,7 @@ typedef struct mi_problem {
    * in single calls and the graph / sequential batch modes, FP4 in single
    * calls and every batch mode; the server takes the byte layout only. */
   int32_t packed;
-  /* mi_gram.  MI_GRAM_FP4 needs byte or FP4 input; MI_GRAM_INT8 byte or bit
-   * input.  Batches and the server follow each problem's choice (byte input
+  /* mi_gram.  MI_GRAM_INT8 needs byte or bit input; MI_GRAM_FP4 any input.  Batches and the server follow each problem's choice (byte input
    * converted in library scratch; the server charges that buffer to the
    * request's HBM budget). */
   int32_t gram;

@@ -48,6 +48,8 @@ constexpr int KT = 64;  // samples per stage = one MFMA K step
 // Input layouts of the plain kernel: 0/1 bytes, 8 columns per byte (bits),
 // or 2 columns per byte as E2M1 (FP4) codes for the FP4 matrix path.
 constexpr int kInBytes = 0, kInBits = 1, kInFp4 = 2;
+// Bit-packed input unpacked on chip to FP4 codes for the FP4 Gram.
+constexpr int kInBitsFp4 = 3;
 constexpr int KT4 = 128;  // samples per stage of the FP4 layout: two K steps of 64
 // An FP4 unit accumulates in FP32, exact for counts up to 2^24: at most this
 // many rows per unit.
@@ -314,7 +316,9 @@ template <class C, int IN = kInBytes>
 __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1, const Smem<C>& sm) {
 #if defined(__HIP_DEVICE_COMPILE__)  // device-only body (gfx950 builtins and asm)
   constexpr int BT = C::BT, FM = C::FM, FN = C::FN;
-  constexpr bool PK = IN == kInBits, F4 = IN == kInFp4;
+  // PK: bits unpacked to bytes (int8 Gram); PK4: bits unpacked to FP4 codes;
+  // F4: the FP4 Gram (FP4 input by DMA, or PK4).
+  constexpr bool PK = IN == kInBits, PK4 = IN == kInBitsFp4, F4 = IN == kInFp4 || PK4;
   constexpr int KS = F4 ? KT4 : KT;  // sample rows per stage
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -338,7 +342,7 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   // physical segment l % SEGS, which holds logical segment (l % SEGS) ^ f(row).
   int voff[C::LOADS];
   uint32_t ldsoff[C::LOADS];
-  if constexpr (F4) {
+  if constexpr (F4 && !PK4) {
     // The same regions over 128 rows of BT / 2 bytes (ROWS_PER_REGION4 rows each).
 #pragma unroll
     for (int i = 0; i < C::LOADS; ++i) {
@@ -350,7 +354,7 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       voff[i] = row * (int)P.ldx + col0 + 16 * seg;
       ldsoff[i] = (uint32_t)R * 1024u;
     }
-  } else if constexpr (!PK) {
+  } else if constexpr (!PK && !PK4) {
 #pragma unroll
     for (int i = 0; i < C::LOADS; ++i) {
       const int R = i * C::NWAVES + wave;
@@ -374,6 +378,17 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
 #pragma unroll
     for (int g = 0; g < 4; ++g)
       pwoff[g] = (uint32_t)(panel * C::PANEL + row * BT + (((4 * q + g) ^ seg_swz<BT>(row)) << 4));
+  }
+  // Bits to FP4 codes: thread tid owns 128 columns (16 packed bytes, four
+  // 32-column FP4 segments) of one of the stage's 128 rows of one panel.
+  constexpr int TPR4 = BT / 128;
+  static_assert(2 * KT4 * TPR4 == C::NT, "one 16-byte packed piece per thread and FP4 stage");
+  if constexpr (PK4) {
+    const int panel = tid / (KT4 * TPR4), row = (tid / TPR4) % KT4, q = tid % TPR4;
+    pvoff = row * (int)P.ldx + ((panel == 0 ? I : J) * BT) / 8 + 16 * q;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      pwoff[g] = (uint32_t)(panel * C::PANEL + row * C::RB4 + (((4 * q + g) ^ seg_swz4<BT>(row)) << 4));
   }
   // Stage j of the unit starts at row k0 + j KS; its base address advances by
   // KS * ldx bytes per stage (scalar adds, no per-stage multiplies).
@@ -480,6 +495,42 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   };
 
   const int rows = k1 - k0;
+  // FP4 Gram (both FP4 paths): FP32 accumulators and one 64-sample K step.
+  // Column sums: a one is the code 0b0010, so a fragment's popcount is its
+  // count of ones.
+  v16f accf[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) accf[a][b][r] = 0.0f;
+  auto mma_half4 = [&](const v4i (&fa)[FM], const v4i (&fb)[FN]) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        accf[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+            v8i{fa[a].x, fa[a].y, fa[a].z, fa[a].w, 0, 0, 0, 0}, v8i{fb[b].x, fb[b].y, fb[b].z, fb[b].w, 0, 0, 0, 0},
+            accf[a][b], 4, 4, 0, 127, 0, 127);  // E2M1 x E2M1, scales 2^0
+#pragma unroll
+    for (int x = 0; x < SA; ++x)
+      csA[x] += (__builtin_popcount((uint32_t)fa[x].x) + __builtin_popcount((uint32_t)fa[x].y)) +
+                (__builtin_popcount((uint32_t)fa[x].z) + __builtin_popcount((uint32_t)fa[x].w));
+#pragma unroll
+    for (int y = 0; y < SB; ++y)
+      csB[y] += (__builtin_popcount((uint32_t)fb[y].x) + __builtin_popcount((uint32_t)fb[y].y)) +
+                (__builtin_popcount((uint32_t)fb[y].z) + __builtin_popcount((uint32_t)fb[y].w));
+  };
+  // Counts of at most 2^24 rows are exact in FP32.
+  auto fp4_counts = [&]() {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[a][b][r] = (int)accf[a][b][r];
+  };
   if constexpr (PK) {
     // Stage j's 8 packed bytes of this thread (zeros past the unit's rows).
     auto pload = [&](uint64_t base, int rem) -> uint2 {
@@ -547,34 +598,75 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
         pkB[y] = 0u;
       }
     }
-  } else if constexpr (F4) {
-    // The byte loop's schedule over 128-row FP4 stages; each half is one
-    // 64-sample K step of the FP4 instruction.  Column sums: a one is the
-    // code 0b0010, so a fragment's popcount is its count of ones.
-    v16f accf[FM][FN];
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-      for (int b = 0; b < FN; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) accf[a][b][r] = 0.0f;
-    auto mma_half4 = [&](const v4i (&fa)[FM], const v4i (&fb)[FN]) {
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-          accf[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-              v8i{fa[a].x, fa[a].y, fa[a].z, fa[a].w, 0, 0, 0, 0}, v8i{fb[b].x, fb[b].y, fb[b].z, fb[b].w, 0, 0, 0, 0},
-              accf[a][b], 4, 4, 0, 127, 0, 127);  // E2M1 x E2M1, scales 2^0
-#pragma unroll
-      for (int x = 0; x < SA; ++x)
-        csA[x] += (__builtin_popcount((uint32_t)fa[x].x) + __builtin_popcount((uint32_t)fa[x].y)) +
-                  (__builtin_popcount((uint32_t)fa[x].z) + __builtin_popcount((uint32_t)fa[x].w));
-#pragma unroll
-      for (int y = 0; y < SB; ++y)
-        csB[y] += (__builtin_popcount((uint32_t)fb[y].x) + __builtin_popcount((uint32_t)fb[y].y)) +
-                  (__builtin_popcount((uint32_t)fb[y].z) + __builtin_popcount((uint32_t)fb[y].w));
+  } else if constexpr (PK4) {
+    // The bit-packed schedule over 128-row FP4 stages: each stage is one
+    // 16-byte load per thread, four stages ahead, unpacked to FP4 codes in
+    // two halves beside the half-steps' instructions.  A packed byte spreads
+    // to one nibble per bit (three shift-or-mask steps), then to the code
+    // 0b0010 per one.
+    auto pload4 = [&](uint64_t base, int rem) -> uint4 {
+      const __amdgpu_buffer_rsrc_t rs = stage_rsrc(base, rem, ldx32, KT4);
+      const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, pvoff, 0, 0);
+      return make_uint4((uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w);
     };
+    auto spread8 = [](uint32_t b) {  // bit k of b -> 0b0010 in nibble k
+      uint32_t t = b & 0xFFu;
+      t = (t | (t << 12)) & 0x000F000Fu;
+      t = (t | (t << 6)) & 0x03030303u;
+      t = (t | (t << 3)) & 0x11111111u;
+      return t << 1;
+    };
+    auto seg4 = [&](uint32_t w) {  // 32 columns (4 packed bytes) -> one 16-byte FP4 segment
+      return make_uint4(spread8(w), spread8(w >> 8), spread8(w >> 16), spread8(w >> 24));
+    };
+    auto pstore_lo4 = [&](uint4 v, uint8_t* slot) {
+      *(MI_LDS uint4*)(slot + pwoff[0]) = seg4(v.x);
+      *(MI_LDS uint4*)(slot + pwoff[1]) = seg4(v.y);
+    };
+    auto pstore_hi4 = [&](uint4 v, uint8_t* slot) {
+      *(MI_LDS uint4*)(slot + pwoff[2]) = seg4(v.z);
+      *(MI_LDS uint4*)(slot + pwoff[3]) = seg4(v.w);
+    };
+    auto write_barrier = [&]() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
+    uint4 pk0 = pload4(xk0, rows), pk1 = pload4(xk0 + stage_bytes, rows - KS);
+    uint4 pk2 = pload4(xk0 + 2 * stage_bytes, rows - 2 * KS), pk3 = pload4(xk0 + 3 * stage_bytes, rows - 3 * KS);
+    pstore_lo4(pk0, sm.slot[0]);
+    pstore_hi4(pk0, sm.slot[0]);
+    pstore_lo4(pk1, sm.slot[1]);
+    pstore_hi4(pk1, sm.slot[1]);
+    pk0 = pload4(xk0 + 4 * stage_bytes, rows - 4 * KS);
+    pk1 = pload4(xk0 + 5 * stage_bytes, rows - 5 * KS);
+    write_barrier();
+    read_half(sm.slot[0], 0, fa0, fb0);
+    uint64_t pbase = xk0 + 6 * stage_bytes;  // stage step + 6, loaded during step `step`
+    int prem = rows - 6 * KS;
+    auto do_step_pk4 = [&](uint8_t* cur, uint8_t* nxt, uint8_t* ahead, uint4& reg) {
+      read_half(cur, 1, fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_half4(fa0, fb0);
+      __builtin_amdgcn_sched_barrier(0);
+      pstore_lo4(reg, ahead);
+      write_barrier();
+      read_half(nxt, 0, fa0, fb0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_half4(fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+      pstore_hi4(reg, ahead);
+      reg = pload4(pbase, prem);
+      pbase += stage_bytes;
+      prem -= KS;
+    };
+    const int nstages = (rows + KS - 1) / KS;
+    for (int step = 0; step < nstages; step += 4) {
+      do_step_pk4(sm.slot[0], sm.slot[1], sm.slot[2], pk2);
+      do_step_pk4(sm.slot[1], sm.slot[2], sm.slot[3], pk3);
+      do_step_pk4(sm.slot[2], sm.slot[3], sm.slot[0], pk0);
+      do_step_pk4(sm.slot[3], sm.slot[0], sm.slot[1], pk1);
+    }
+    fp4_counts();
+  } else if constexpr (F4) {
+    // The byte loop's schedule over 128-row FP4 stages (DMA); each half is
+    // one 64-sample K step of the FP4 instruction.
     dma_stage(xk0, rows, sm.slot[0]);
     dma_stage(xk0 + stage_bytes, rows - KS, sm.slot[1]);
     dma_stage(xk0 + 2 * stage_bytes, rows - 2 * KS, sm.slot[2]);
@@ -604,13 +696,7 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       do_step4(sm.slot[2], sm.slot[3]);
       do_step4(sm.slot[3], sm.slot[0]);
     }
-    // Counts of at most 2^24 rows are exact in FP32.
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-      for (int b = 0; b < FN; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[a][b][r] = (int)accf[a][b][r];
+    fp4_counts();
   } else {
   // Prologue: stages 0 .. 2 in flight in slots 0 .. 2; once stage 0 is in,
   // stage 3 goes to slot 3 and the first half of stage 0 is read.

@@ -286,6 +286,8 @@ static hipError_t launch_plain_c(const ProbDev& P, hipStream_t st) {
   const int64_t grid = 8LL * P.tiles_per_xcd * P.splits;
   if (P.packed == kInFp4)
     hipLaunchKernelGGL((k_plain<C, kInFp4>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
+  else if (P.packed == kInBitsFp4)
+    hipLaunchKernelGGL((k_plain<C, kInBitsFp4>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
   else if (P.packed == kInBits)
     hipLaunchKernelGGL((k_plain<C, kInBits>), dim3((unsigned)grid), dim3(C::NT), 0, st, P);
   else

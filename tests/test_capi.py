@@ -224,7 +224,7 @@ def test_packed_argument_checks(L):
 def test_fp4_argument_checks(L):
     """FP4 input (2 columns per byte) and the Gram choice: pitch in bytes of 2
     columns and at most 2^23, no validate, no sparse algorithm, no int8 Gram;
-    bit input takes no FP4 Gram; batches check each problem the same way;
+    batches check each problem the same way;
     the packing utility checks its pitches."""
     from paper_2411_19702_amd import mi
     def prob(**kw):
@@ -240,7 +240,6 @@ def test_fp4_argument_checks(L):
     assert ex(algo=mi.MI_ALGO_SPARSE) == 1
     assert ex(ldx=(1 << 23) + 16) == 1                         # 128-row stages, 32-bit offsets
     assert ex(packed=3) == 1 and ex(gram=3) == 1 and ex(gram=-1) == 1
-    assert ex(packed=mi.MI_INPUT_BITS, ldx=3, gram=mi.MI_GRAM_FP4) == 1
     assert ex(packed=mi.MI_INPUT_BYTES, ldx=17, gram=mi.MI_GRAM_FP4, algo=mi.MI_ALGO_SPARSE) == 1
     for mode in (mi.MI_BATCH_PERSISTENT, mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL):
         arr = (mi.mi_problem * 1)(prob(gram=mi.MI_GRAM_INT8))

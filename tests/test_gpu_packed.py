@@ -148,3 +148,60 @@ def test_packed_in_batches(mode):
             mi.mi_all_pairs_ex(X, out=want)
             torch.cuda.synchronize()
             assert torch.equal(o, want)
+
+
+@pytest.mark.parametrize("m,n", CASES)
+def test_packed_bits_on_fp4_gram_equal_bytes(m, n):
+    """Bits unpacked on chip to FP4 codes (gram = FP4): MI, n11 and column sums
+    bitwise equal to the byte layout on the int8 Gram; small cases against the oracle."""
+    say(f"[packed fp4] {m}x{n}")
+    spec = synth.spec_random(9 * m + n, m, n, 0.0, 1.0, planted=max(1, n // 20))
+    X = synth.generate(spec, device=DEV)
+    P = mi.mi_pack_bits(X, n)
+    b = _run(X, n, False, gram=mi.MI_GRAM_INT8)
+    p = _run(P, n, True, gram=mi.MI_GRAM_FP4)
+    for x, y, name in zip(b, p, ("MI", "n11", "column sums")):
+        assert torch.equal(x, y), f"bits on the FP4 Gram: {name} differ from the byte layout"
+    if m * n <= 1_000_000:
+        compare_full(X.cpu().numpy(), n, p[0].cpu().numpy(), p[1].cpu().numpy(), p[2].cpu().numpy()[:n])
+
+
+@pytest.mark.parametrize("tile,splits", [(1, 1), (2, 1), (1, 5), (2, 3)])
+def test_packed_bits_on_fp4_gram_configurations(tile, splits):
+    spec = synth.spec_random(45, 30000, 700, 0.0, 0.5, planted=10)
+    X = synth.generate(spec, device=DEV)
+    P = mi.mi_pack_bits(X)
+    b = _run(X, 700, False, tile=tile, splits=splits, gram=mi.MI_GRAM_INT8)
+    p = _run(P, 700, True, tile=tile, splits=splits, gram=mi.MI_GRAM_FP4)
+    for x, y in zip(b, p):
+        assert torch.equal(x, y)
+
+
+def test_packed_bits_on_fp4_gram_large_workload_and_batches():
+    """The 1,000,000 x 4,096 workload from bits on the FP4 Gram, bitwise equal
+    to the byte path; bits-on-FP4 problems in graph and sequential batches."""
+    spec = synth.spec_large()
+    say(f"[packed fp4] {spec.m}x{spec.n}")
+    X = synth.generate(spec, device=DEV)
+    P = mi.mi_pack_bits(X)
+    out_b = torch.empty((spec.n, spec.n), device=DEV)
+    out_p = torch.empty((spec.n, spec.n), device=DEV)
+    mi.mi_all_pairs_ex(X, out=out_b, gram=mi.MI_GRAM_INT8)
+    mi.mi_all_pairs_ex(P, out=out_p, n=spec.n, packed=True, gram=mi.MI_GRAM_FP4)
+    torch.cuda.synchronize()
+    assert torch.equal(out_b, out_p)
+    del X, P, out_b, out_p
+    specs = [synth.spec_random(960 + k, 3000 + 700 * k, 90 + 41 * k, 0.0, 0.8, planted=3) for k in range(3)]
+    Xs = [synth.generate(s, device=DEV) for s in specs]
+    Ps = [mi.mi_pack_bits(X) for X in Xs]
+    for mode in (mi.MI_BATCH_GRAPH, mi.MI_BATCH_SEQUENTIAL):
+        outs = [torch.full((s.n, s.n), float("nan"), device=DEV) for s in specs]
+        probs = [mi.make_problem(P, o, n=s.n, packed=True, gram=mi.MI_GRAM_FP4) for P, o, s in zip(Ps, outs, specs)]
+        for _ in range(2):
+            mi.mi_all_pairs_batched(probs, mode=mode)
+            torch.cuda.synchronize()
+            for X, o in zip(Xs, outs):
+                want = torch.empty_like(o)
+                mi.mi_all_pairs_ex(X, out=want, gram=mi.MI_GRAM_INT8)
+                torch.cuda.synchronize()
+                assert torch.equal(o, want)
