@@ -153,7 +153,8 @@ typedef struct mi_problem {
    * in single calls and the graph / sequential batch modes, FP4 in single
    * calls and every batch mode; the server takes the byte layout only. */
   int32_t packed;
-  /* mi_gram.  MI_GRAM_INT8 needs byte or bit input; MI_GRAM_FP4 any input.  Batches and the server follow each problem's choice (byte input
+  /* mi_gram.  MI_GRAM_INT8 needs byte or bit input; MI_GRAM_FP4 takes any
+   * input.  Batches and the server follow each problem's choice (byte input
    * converted in library scratch; the server charges that buffer to the
    * request's HBM budget). */
   int32_t gram;
