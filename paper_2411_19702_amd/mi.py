@@ -200,7 +200,8 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
     """pairs: int32 GPU tensor of shape (capacity, 3) receiving (i, j, MI bits as FP32) rows;
     pairs_count: int64 GPU tensor with one element (the number of qualifying pairs).
     packed: False (bytes), True / MI_INPUT_BITS (mi_pack_bits) or MI_INPUT_FP4 (mi_pack_fp4).
-    gram: MI_GRAM_AUTO, MI_GRAM_INT8 or MI_GRAM_FP4 (the Gram's matrix instructions)."""
+    gram: MI_GRAM_AUTO, MI_GRAM_INT8 or MI_GRAM_FP4 (the Gram's matrix instructions).
+    The returned problem keeps references to the tensors it points to."""
     m, n, ldx = _x_layout(X, n, packed)
     for name, t, dt in (("out", out, torch.float32), ("n11_out", n11_out, torch.int32),
                         ("colsum_out", colsum_out, torch.int32), ("pairs", pairs, torch.int32),
@@ -224,6 +225,8 @@ def make_problem(X: torch.Tensor, out: Optional[torch.Tensor], n: Optional[int] 
     p.algo = int(algo)
     p.packed = _layout_code(packed)
     p.gram = int(gram)
+    # The struct holds raw pointers: keep the tensors alive as long as the problem.
+    p._keep = (X, out, n11_out, colsum_out, pairs, pairs_count)
     return p
 
 
