@@ -279,6 +279,11 @@ def bench_categorical(dev, reps: int = 5):
         X = synth.cat_generate(spec, device=dev)
         levels = [int(x) for x in spec.levels]
         out = torch.empty((v, v), dtype=torch.float32, device=dev)
+        # The indicator Gram's matrix instructions: the library's choice for an m x N byte
+        # problem (mi_plan_ex reads only the shape of its placeholder).
+        probe = torch.empty((m, mi.mi_cat_indicators(levels)), dtype=torch.uint8, device=dev)
+        gram = mi.mi_plan_ex(probe)[2]
+        del probe
         mi.mi_all_pairs_categorical(X, levels, out=out)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -289,7 +294,7 @@ def bench_categorical(dev, reps: int = 5):
         N = mi.mi_cat_indicators(levels)
         row = {"workload": f"genotypes_{m}x{v}", "levels": 3, "indicator_columns": N, "ms": t * 1e3,
                "variable_pairs_per_s": v * (v + 1) / 2 / t,
-               "gram_int8_ops_per_s": 2.0 * m * N * (N + 1) / 2 / t}
+               "gram": GRAM_NAMES[gram], "gram_ops_per_s": 2.0 * m * N * (N + 1) / 2 / t}
         res.append(row)
         print(f"[categorical] {row}", file=sys.stderr, flush=True)
         del X, out
@@ -619,20 +624,20 @@ def main() -> int:
     # on the converted input (same kernel, plan and stream).
     conversion = None
     avg_kernel_s, in_bytes = avg_step_s, m * X.stride(0)
+
+    def timed(fn):
+        fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return sum(e0.elapsed_time(e1) for e0, e1 in evs) / len(evs) / 1e3
+
     if gram == mi.MI_GRAM_FP4:
         Q = mi.mi_pack_fp4(X)
         kq = dict(kw, gram=mi.MI_GRAM_AUTO)
-
-        def timed(fn):
-            fn()
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-            for e0, e1 in evs:
-                e0.record(stream)
-                fn()
-                e1.record(stream)
-            torch.cuda.synchronize()
-            return sum(e0.elapsed_time(e1) for e0, e1 in evs) / len(evs) / 1e3
-
         avg_kernel_s = timed(lambda: mi.mi_all_pairs_ex(Q, out=out, n=n, packed=mi.MI_INPUT_FP4, stream=stream, **kq))
         conv_s = timed(lambda: mi.mi_pack_fp4(X, out=Q, stream=stream))
         in_bytes = Q.numel()
@@ -643,6 +648,16 @@ def main() -> int:
     pu_per_step = m * n * (n + 1) / 2
     value = pu_per_step * args.steps / wall
     achieved = 2.0 * pu_per_step / avg_kernel_s
+    # The fused kernel on the int8 Gram (int8 x int8 -> int32 matrix instructions on the
+    # bytes), timed the same way on the same matrix: its fraction of the int8 peak.
+    int8_kernel = None
+    if gram == mi.MI_GRAM_FP4 and m >= OUTPUT_BOUND_ROWS:
+        k8 = dict(kw, gram=mi.MI_GRAM_INT8)
+        tile8, splits8, _ = mi.mi_plan_ex(X, **k8)
+        t8 = timed(lambda: mi.mi_all_pairs_ex(X, out=out, stream=stream, **k8))
+        int8_kernel = {"kernel": plain_kernel_name(tile8, mi.MI_GRAM_INT8), "tile": [None, 128, 256][tile8],
+                       "splits": splits8, "ms": t8 * 1e3, "achieved_TOPS": 2.0 * pu_per_step / t8 / 1e12,
+                       "frac_int8_peak": 2.0 * pu_per_step / t8 / PEAK_INT8_OPS}
     traffic = load_traffic(args.workload, [None, 128, 256][tile], splits, plain_kernel_name(tile, gram))
     rec = {
         "metric": "MI pair-updates/s (m*n(n+1)/2) & % int8 MFMA peak; p50/p99 request latency",
@@ -665,6 +680,9 @@ def main() -> int:
             "conversion": conversion, "step_ms_on_stream": avg_step_s * 1e3,
         },
         "roofline": roofline(m, in_bytes, n, avg_kernel_s, achieved, traffic, tile, gram),
+        # End to end (conversion included), 2 ops per pair-update, against the int8 peak.
+        "frac_int8_peak": 2.0 * value / PEAK_INT8_OPS,
+        "int8_kernel": int8_kernel,
     }
     del X
     torch.cuda.empty_cache()

@@ -126,7 +126,8 @@ typedef struct mi_problem {
   int32_t* colsum_out;   /* optional device int32[n]: column sums c                 */
   int32_t epilogue;      /* mi_epilogue                                             */
   float fallback_tau;    /* MI_EPI_FP32_FP64_FALLBACK threshold in bits; <= 0: 1e-3  */
-  int32_t validate;      /* nonzero: check X is 0/1 first (one extra pass, blocking) */
+  int32_t validate;      /* nonzero: check X is 0/1 first (one extra pass, blocking); */
+                         /* FP4 input: every code 0 or 0b0010                       */
   int32_t tile;          /* mi_tile; 0 = autotuned / heuristic                      */
   int32_t splits;        /* K-splits over the rows; 0 = autotuned / heuristic       */
   /* Sparse output (blockwise use when the n x n matrix is not wanted or does
@@ -147,8 +148,9 @@ typedef struct mi_problem {
    * for the int8 Gram, to FP4 codes for the FP4 Gram); validate is a no-op
    * (every bit is 0 or 1).  MI_INPUT_FP4: X holds 2 columns per byte,
    * column 2 c in the low nibble of byte c, each nibble 0b0010 (a one) or 0
-   * (as mi_pack_fp4 writes them; other codes give undefined counts); ldx >=
-   * ceil(n / 2), at most 2^23; validate must be 0.  Results are the same as
+   * (as mi_pack_fp4 writes them; other codes give undefined counts unless
+   * validate is set, which then checks every code of columns < n and returns
+   * MI_ERR_NOT_BINARY); ldx >= ceil(n / 2), at most 2^23.  Results are the same as
    * for the byte layout.  Packed layouts take the dense algorithm only; bits
    * in single calls and the graph / sequential batch modes, FP4 in single
    * calls and every batch mode; the server takes the byte layout only. */

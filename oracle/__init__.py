@@ -49,6 +49,10 @@ def _load():
         lib.mi_oracle_all.restype = ctypes.c_int
         lib.mi_oracle_colsums.argtypes = [p, i64, i64, i64, p]
         lib.mi_oracle_colsums.restype = ctypes.c_int
+        lib.mi_oracle_pairs_t.argtypes = [p, i64, i64, i64, i64, p, p, p, p, p, p, p]
+        lib.mi_oracle_pairs_t.restype = ctypes.c_int
+        lib.mi_oracle_colsums_t.argtypes = [p, i64, i64, i64, p]
+        lib.mi_oracle_colsums_t.restype = ctypes.c_int
         lib.mi_oracle_from_counts.argtypes = [i64, i64, i64, i64]
         lib.mi_oracle_from_counts.restype = ctypes.c_double
         i32 = ctypes.c_int32
@@ -111,6 +115,41 @@ def pairs(X, pi, pj, n: Optional[int] = None):
     if rc != 0:
         raise ValueError(f"mi_oracle_pairs rc={rc}")
     return out
+
+
+def pairs_t(Xt, pi, pj, n: Optional[int] = None):
+    """pairs() on the transposed layout: Xt is (cols, m), row j holding column j's m entries."""
+    Xt = _as_u8(Xt)
+    ncols, m = Xt.shape
+    n = ncols if n is None else n
+    pi = np.ascontiguousarray(pi, dtype=np.int64)
+    pj = np.ascontiguousarray(pj, dtype=np.int64)
+    if pi.shape != pj.shape or pi.ndim != 1:
+        raise ValueError("pi and pj must be 1-D and the same length")
+    if n > ncols:
+        raise ValueError("n exceeds the rows of Xt")
+    k = pi.shape[0]
+    out = {name: np.empty(k, dtype=np.int64) for name in ("n11", "n10", "n01", "n00")}
+    out["mi"] = np.empty(k, dtype=np.float64)
+    rc = _load().mi_oracle_pairs_t(_ptr(Xt), m, n, m, k, _ptr(pi), _ptr(pj), _ptr(out["n11"]), _ptr(out["n10"]),
+                                   _ptr(out["n01"]), _ptr(out["n00"]), _ptr(out["mi"]))
+    if rc != 0:
+        raise ValueError(f"mi_oracle_pairs_t rc={rc}")
+    return out
+
+
+def colsums_t(Xt, n: Optional[int] = None) -> np.ndarray:
+    """colsums() on the transposed layout (cols, m)."""
+    Xt = _as_u8(Xt)
+    ncols, m = Xt.shape
+    n = ncols if n is None else n
+    if n > ncols:
+        raise ValueError("n exceeds the rows of Xt")
+    c = np.empty(n, dtype=np.int64)
+    rc = _load().mi_oracle_colsums_t(_ptr(Xt), m, n, m, _ptr(c))
+    if rc != 0:
+        raise ValueError(f"mi_oracle_colsums_t rc={rc}")
+    return c
 
 
 def colsums(X, n: Optional[int] = None) -> np.ndarray:

@@ -40,14 +40,16 @@ static double cell_term(int64_t nxy, int64_t nx, int64_t ny, int64_t m)
     return (double)nxy * log2(num / den);
 }
 
-/* Count the four cells of the pair (i, j) by looping over the rows. */
-static void count_pair(const uint8_t* X, int64_t m, int64_t ldx, int64_t i, int64_t j,
+/* Count the four cells of a pair of columns by looping over the rows.  Row k
+ * of column i is xi[k * stride] (stride = ldx for the row-major X, 1 for a
+ * column of the transposed layout), likewise for column j. */
+static void count_pair(const uint8_t* xcol_i, const uint8_t* xcol_j, int64_t m, int64_t stride,
                        int64_t* n11, int64_t* n10, int64_t* n01, int64_t* n00)
 {
     int64_t a = 0, b = 0, c = 0, d = 0;
     for (int64_t k = 0; k < m; ++k) {
-        int xi = X[k * ldx + i] != 0;
-        int xj = X[k * ldx + j] != 0;
+        int xi = xcol_i[k * stride] != 0;
+        int xj = xcol_j[k * stride] != 0;
         if (xi && xj) ++a;
         else if (xi && !xj) ++b;
         else if (!xi && xj) ++c;
@@ -96,7 +98,44 @@ int mi_oracle_pairs(const uint8_t* X, int64_t m, int64_t n, int64_t ldx,
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t p = 0; p < npairs; ++p) {
         int64_t a, b, c, d;
-        count_pair(X, m, ldx, pi[p], pj[p], &a, &b, &c, &d);
+        count_pair(X + pi[p], X + pj[p], m, ldx, &a, &b, &c, &d);
+        if (n11) n11[p] = a;
+        if (n10) n10[p] = b;
+        if (n01) n01[p] = c;
+        if (n00) n00[p] = d;
+        if (mi) mi[p] = mi_oracle_from_counts(a, b, c, d);
+    }
+    return 0;
+}
+
+/*
+ * The same two functions on the transposed layout: Xt is n x ldt bytes, row j
+ * holding the m entries of column j (ldt >= m).  Only the addressing differs
+ * (a column is contiguous), which makes a long column sample cheap to check.
+ */
+int mi_oracle_colsums_t(const uint8_t* Xt, int64_t m, int64_t n, int64_t ldt, int64_t* c)
+{
+    if (!Xt || !c || m <= 0 || n < 0 || ldt < m) return 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t s = 0;
+        for (int64_t k = 0; k < m; ++k) s += Xt[j * ldt + k] != 0;
+        c[j] = s;
+    }
+    return 0;
+}
+
+int mi_oracle_pairs_t(const uint8_t* Xt, int64_t m, int64_t n, int64_t ldt,
+                      int64_t npairs, const int64_t* pi, const int64_t* pj,
+                      int64_t* n11, int64_t* n10, int64_t* n01, int64_t* n00, double* mi)
+{
+    if (!Xt || m <= 0 || n < 0 || ldt < m || npairs < 0 || (npairs > 0 && (!pi || !pj))) return 1;
+    for (int64_t p = 0; p < npairs; ++p)
+        if (pi[p] < 0 || pi[p] >= n || pj[p] < 0 || pj[p] >= n) return 2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npairs; ++p) {
+        int64_t a, b, c, d;
+        count_pair(Xt + pi[p] * ldt, Xt + pj[p] * ldt, m, 1, &a, &b, &c, &d);
         if (n11) n11[p] = a;
         if (n10) n10[p] = b;
         if (n01) n01[p] = c;
@@ -118,7 +157,7 @@ int mi_oracle_all(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int64_t* 
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = i; j < n; ++j) {
             int64_t a, b, c, d;
-            count_pair(X, m, ldx, i, j, &a, &b, &c, &d);
+            count_pair(X + i, X + j, m, ldx, &a, &b, &c, &d);
             double v = mi_oracle_from_counts(a, b, c, d);
             if (n11) { n11[i * n + j] = a; n11[j * n + i] = a; }
             if (mi)  { mi[i * n + j] = v;  mi[j * n + i] = v; }

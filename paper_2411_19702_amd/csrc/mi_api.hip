@@ -325,8 +325,6 @@ mi_status check_problem(const mi_problem* p, int64_t* ldx_out, bool need_output)
   if (p->gram < MI_GRAM_AUTO || p->gram > MI_GRAM_FP4) return fail(MI_ERR_INVALID_ARG, "bad gram %d", p->gram);
   if (p->packed == MI_INPUT_FP4 && p->gram == MI_GRAM_INT8)
     return fail(MI_ERR_INVALID_ARG, "FP4 input takes the FP4 Gram");
-  if (p->packed == MI_INPUT_FP4 && p->validate)
-    return fail(MI_ERR_INVALID_ARG, "validate is not available for FP4 input (validate the bytes before packing)");
   if (p->packed && p->algo != MI_ALGO_DENSE)
     return fail(MI_ERR_INVALID_ARG, "packed input takes only the dense algorithm");
   if (p->gram == MI_GRAM_FP4 && p->algo == MI_ALGO_SPARSE)
@@ -404,10 +402,12 @@ mi_status validate_binary(const mi_problem* p, int64_t ldx, hipStream_t st) {
     if (!f) HIPCHK(hipMalloc(&f, 256));
     flag = f;
   }
-  HIPCHK(launch_validate(p->X, p->m, p->n, ldx, flag, st));
+  const bool fp4 = p->packed == MI_INPUT_FP4;
+  HIPCHK(fp4 ? launch_validate_fp4(p->X, p->m, p->n, ldx, flag, st) : launch_validate(p->X, p->m, p->n, ldx, flag, st));
   int h = 0;
   HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (h && fp4) return fail(MI_ERR_NOT_BINARY, "X holds an FP4 code other than 0 and 0b0010 (1.0)");
   if (h) return fail(MI_ERR_NOT_BINARY, "X holds a byte other than 0 or 1");
   return MI_OK;
 }
@@ -418,7 +418,7 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_o
   if (s != MI_OK) return s;
   if (p->pairs) HIPCHK(fill_i32(reinterpret_cast<int*>(p->pairs_count), 0, 2, st));  // 64-bit counter
   if (p->n == 0) return MI_OK;
-  if (p->validate && !p->packed) {  // packed bits are 0 or 1 by construction
+  if (p->validate && p->packed != MI_INPUT_BITS) {  // packed bits are 0 or 1 by construction
     s = validate_binary(p, ldx, st);
     if (s != MI_OK) return s;
   }
@@ -496,7 +496,7 @@ static std::string batch_key(const mi_problem* probs, int64_t count, const std::
              p.epilogue, (double)p.fallback_tau, plans[d].cfg, plans[d].splits, (void*)p.pairs,
              (long long)p.pairs_capacity, (void*)p.pairs_count, (double)p.pairs_threshold);
     k += buf;
-    snprintf(buf, sizeof buf, "%d,%d;", p.packed, converts_to_fp4(&p) ? 1 : 0);
+    snprintf(buf, sizeof buf, "%d,%d,%d,%d;", p.packed, p.gram, converts_to_fp4(&p) ? 1 : 0, runs_fp4(&p) ? 1 : 0);
     k += buf;
   }
   return k;

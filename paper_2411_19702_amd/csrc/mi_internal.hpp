@@ -38,6 +38,7 @@ hipError_t launch_plain(int cfg, const ProbDev& P, hipStream_t st);
 hipError_t launch_persistent(int cfg, bool fp4, const ProbDev* probs, const UnitRef* units, int nunits, int* head,
                              int grid, hipStream_t st);
 hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st);
+hipError_t launch_validate_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st);
 hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Y, int64_t ldy,
                          hipStream_t st);
 hipError_t launch_repack_batch(const RepackDesc* descs, int count, int64_t blocks, hipStream_t st);

@@ -75,6 +75,23 @@ __global__ void k_validate(const uint8_t* __restrict__ X, int64_t m, int64_t n, 
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// flag |= (some column c < n of X, in the FP4 layout, holds a code other than
+// 0 and 0b0010).  Columns 2 b and 2 b + 1 are the low and high nibble of byte
+// b; the high nibble of the last byte is ignored when n is odd.
+__global__ void k_validate_fp4(const uint8_t* __restrict__ X, int64_t m, int64_t n, int64_t ldx, int* flag) {
+  const int64_t nb = (n + 1) / 2;
+  int bad = 0;
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    const uint8_t* r = X + row * ldx;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+      const uint32_t v = r[b];
+      const uint32_t lo = v & 0xFu, hi = (2 * b + 1 < n) ? (v >> 4) : 0u;
+      bad |= (lo != 0u && lo != 2u) || (hi != 0u && hi != 2u);
+    }
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 // Byte -> FP4 packing (the layout of the FP4 path): two columns per byte,
 // column 2 c in the low nibble of byte c, the E2M1 code of 1.0 (0b0010) for a
 // nonzero byte and 0 for a zero.  Four input bytes give 16 output bits: bit 7
@@ -319,6 +336,13 @@ hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, 
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, flag, 0, 1);
   const int64_t blocks = m < 4096 ? m : 4096;
   hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, st, X, m, n, ldx, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, flag, 0, 1);
+  const int64_t blocks = m < 4096 ? m : 4096;
+  hipLaunchKernelGGL(k_validate_fp4, dim3((unsigned)blocks), dim3(256), 0, st, X, m, n, ldx, flag);
   return hipGetLastError();
 }
 

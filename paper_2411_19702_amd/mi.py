@@ -336,7 +336,7 @@ class Server:
         p = make_problem(X, out, **kw)
         t = ctypes.c_uint64()
         _check(lib().mi_server_submit(self._h, ctypes.byref(p), ctypes.byref(t)))
-        self._keep[t.value] = (X, out) + tuple(keep)
+        self._keep[t.value] = (p._keep, tuple(keep))  # every tensor the request reads or writes
         return t.value
 
     def poll(self, ticket: int) -> bool:

@@ -95,6 +95,36 @@ def check_golden(impl, tol: float = 1e-15) -> None:
         assert abs(float(mi[1, 0]) - case["mi_bits"]) <= tol, (case["name"], float(mi[1, 0]), case["mi_bits"])
 
 
+def check_cells(pairs_impl) -> None:
+    """The four cell counts of a pair list, each on its own (MI is symmetric in
+    the two variables, so a swap of n10 and n01 leaves it unchanged and only a
+    check of the cells themselves can see it).
+
+    pairs_impl(X, pi, pj) returns a dict with int arrays n11, n10, n01, n00 for
+    the pairs (pi[k], pj[k]).  Checked against the hand counts of the golden
+    cases in both orders (n10 of (i, j) is n01 of (j, i)), and against the
+    definitions counted by enumeration on every 2-column matrix of 1..6 rows:
+    n10 = #{X_i = 1, X_j = 0}, n01 = #{X_i = 0, X_j = 1}."""
+    with open(GOLDEN) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        X = np.stack([np.array(case["x"], dtype=np.uint8), np.array(case["y"], dtype=np.uint8)], axis=1)
+        r = pairs_impl(X, [0, 1], [1, 0])
+        got = [(int(r["n11"][k]), int(r["n10"][k]), int(r["n01"][k]), int(r["n00"][k])) for k in (0, 1)]
+        want = (case["n11"], case["n10"], case["n01"], case["n00"])
+        assert got[0] == want, (case["name"], "(x, y)", got[0], want)
+        assert got[1] == (want[0], want[2], want[1], want[3]), (case["name"], "(y, x)", got[1])
+    for m in range(1, 7):
+        for bits in itertools.product((0, 1), repeat=2 * m):
+            X = np.array(bits, dtype=np.uint8).reshape(m, 2)
+            r = pairs_impl(X, [0, 1, 0], [1, 0, 0])
+            for k, (i, j) in enumerate(((0, 1), (1, 0), (0, 0))):
+                xi, xj = X[:, i].tolist(), X[:, j].tolist()
+                want = tuple(sum(1 for a, b in zip(xi, xj) if (a, b) == cell) for cell in ((1, 1), (1, 0), (0, 1), (0, 0)))
+                got = (int(r["n11"][k]), int(r["n10"][k]), int(r["n01"][k]), int(r["n00"][k]))
+                assert got == want, (X.tolist(), i, j, got, want)
+
+
 def check_identities(impl, X: np.ndarray, tol: float = 1e-12) -> None:
     """Symmetry, diagonal = entropy, bounds, and 1-1 counts equal to X^T X."""
     m, n = X.shape

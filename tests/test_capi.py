@@ -223,7 +223,7 @@ def test_packed_argument_checks(L):
 
 def test_fp4_argument_checks(L):
     """FP4 input (2 columns per byte) and the Gram choice: pitch in bytes of 2
-    columns and at most 2^23, no validate, no sparse algorithm, no int8 Gram;
+    columns and at most 2^23, no sparse algorithm, no int8 Gram;
     batches check each problem the same way;
     the packing utility checks its pitches."""
     from paper_2411_19702_amd import mi
@@ -236,7 +236,6 @@ def test_fp4_argument_checks(L):
     ex = lambda **kw: L.mi_all_pairs_ex(ctypes.byref(prob(**kw)), None)
     assert ex(ldx=8) == 1                                      # 17 columns need 9 bytes
     assert ex(gram=mi.MI_GRAM_INT8) == 1                       # FP4 input, int8 Gram
-    assert ex(validate=1) == 1
     assert ex(algo=mi.MI_ALGO_SPARSE) == 1
     assert ex(ldx=(1 << 23) + 16) == 1                         # 128-row stages, 32-bit offsets
     assert ex(packed=3) == 1 and ex(gram=3) == 1 and ex(gram=-1) == 1

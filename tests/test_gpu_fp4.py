@@ -249,11 +249,29 @@ def test_fp4_rejected_where_unsupported():
     out = torch.empty((40, 40), device=DEV)
     with pytest.raises(mi.MIError):
         mi.mi_all_pairs_ex(X, out=out, gram=mi.MI_GRAM_FP4, algo=mi.MI_ALGO_SPARSE)
-    with pytest.raises(mi.MIError):
-        mi.mi_all_pairs_ex(mi.mi_pack_fp4(X), out=out, n=40, packed=mi.MI_INPUT_FP4, validate=True)
     with mi.Server(hbm_budget_bytes=1 << 30) as srv:
         with pytest.raises(mi.MIError):
             srv.submit(mi.mi_pack_fp4(X), out, n=40, packed=mi.MI_INPUT_FP4)
+
+
+def test_fp4_input_validate():
+    """validate on FP4 input: every code of columns < n must be 0 or 0b0010 (MI_ERR_NOT_BINARY
+    otherwise); the unused high nibble of the last byte (odd n) is not checked."""
+    say("[fp4] validate FP4 input")
+    m, n = 777, 41
+    X = synth.generate(synth.spec_random(4242, m, n, 0.0, 0.7, planted=2), device=DEV)
+    Q = mi.mi_pack_fp4(X)
+    want = mi.mi_all_pairs_ex(X, gram=mi.MI_GRAM_INT8)
+    Q[:, -1] |= 0x70                                   # column 41 (past n): ignored
+    got = mi.mi_all_pairs_ex(Q, n=n, packed=mi.MI_INPUT_FP4, validate=True)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    for row, byte, code in ((500, 7, 0x04), (0, 0, 0x30), (m - 1, 20, 0x01)):
+        Qb = Q.clone()
+        Qb[row, byte] = (Qb[row, byte] & 0xF0) | code if code < 0x10 else (Qb[row, byte] & 0x0F) | code
+        with pytest.raises(mi.MIError) as ei:
+            mi.mi_all_pairs_ex(Qb, n=n, packed=mi.MI_INPUT_FP4, validate=True)
+        assert ei.value.status == 2, (row, byte, code)
 
 
 def test_fp4_in_server():

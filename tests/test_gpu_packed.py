@@ -205,3 +205,22 @@ def test_packed_bits_on_fp4_gram_large_workload_and_batches():
                 mi.mi_all_pairs_ex(X, out=want, gram=mi.MI_GRAM_INT8)
                 torch.cuda.synchronize()
                 assert torch.equal(o, want)
+
+
+def test_graph_batches_alternating_gram_on_the_same_buffers():
+    """The graph mode keys its cached graphs by each problem's Gram too: the same bit-packed
+    buffers and plan asked for the int8 and the FP4 Gram in turn replay the graph of the Gram
+    asked for, and every replay equals the byte layout's single call."""
+    say("[packed] graph batches alternating int8 / FP4 Gram")
+    spec = synth.spec_random(961, 5000, 333, 0.0, 0.7, planted=4)
+    X = synth.generate(spec, device=DEV)
+    P = mi.mi_pack_bits(X)
+    want = torch.empty((spec.n, spec.n), device=DEV)
+    mi.mi_all_pairs_ex(X, out=want, gram=mi.MI_GRAM_INT8)
+    out = torch.empty_like(want)
+    for gram in (mi.MI_GRAM_INT8, mi.MI_GRAM_FP4, mi.MI_GRAM_INT8, mi.MI_GRAM_FP4):
+        out.fill_(float("nan"))
+        p = mi.make_problem(P, out, n=spec.n, packed=True, gram=gram, tile=mi.MI_TILE_128, splits=1)
+        mi.mi_all_pairs_batched([p], mode=mi.MI_BATCH_GRAPH)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), gram

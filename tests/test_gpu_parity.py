@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_2411_19702_amd import mi, synth
-from tests.gpu_util import compare_columns, compare_full, run_gpu, say
+from tests.gpu_util import MI_TOL, compare_columns, compare_full, run_gpu, say
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -174,18 +174,65 @@ def test_mid_workload_sampled(epi):
     say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
 
 
-@pytest.mark.parametrize("epi", [0, 1])
-def test_large_workload_sampled(epi):
+@pytest.fixture(scope="module")
+def large_reference():
+    """1,000,000 x 4,096 (the headline workload) on the GPU, and the oracle's answers for
+    every column sum, every diagonal entry, 10,000 seeded random pairs and every pair among
+    the columns on both sides of each 128-column tile boundary (which includes every
+    256-column boundary).  The oracle reads a transposed host copy of the input (each
+    column contiguous), taken before any library call."""
     spec = synth.spec_large()
-    say(f"[parity] large 1000000x4096 epi={epi}")
+    n = spec.n
+    say("[parity] large 1000000x4096: generating, host copy, oracle")
     X = _gen(spec)
-    out, n11, cs = run_gpu(X, epilogue=epi)
+    Xt = X.t().contiguous()
+    Xt_h = Xt.cpu().numpy()
+    del Xt
+    torch.cuda.empty_cache()
+    cs = oracle.colsums_t(Xt_h)
+    rng = np.random.default_rng(241119702 + 12)
+    ri = rng.integers(0, n, size=10_000)
+    rj = rng.integers(0, n, size=10_000)
+    edge = sorted({0, 1, n - 2, n - 1} | {c for b in range(128, n, 128) for c in (b - 1, b)})
+    ei, ej = np.triu_indices(len(edge))
+    edge = np.asarray(edge)
+    pi = np.concatenate([np.arange(n), ri, edge[ei]])
+    pj = np.concatenate([np.arange(n), rj, edge[ej]])
+    ref = oracle.pairs_t(Xt_h, pi, pj)
+    del Xt_h
+    say(f"  oracle: {n} column sums, {len(pi)} pairs ({n} diagonal, 10000 random, {len(ei)} at tile edges)")
+    yield spec, X, cs, pi, pj, ref
     del X
     torch.cuda.empty_cache()
-    cols = _sample_columns(spec, 8, 2)
-    Xs = synth.columns(spec, cols).numpy()
-    err = compare_columns(Xs, cols, out, n11, cs)
-    say(f"  {len(cols)} columns, max|dMI|={err:.3e}")
+
+
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_large_workload_sampled(large_reference, epi):
+    """The headline workload in the benchmark's configuration (the library's own plan and
+    Gram): every column sum bit-exact, the diagonal and >= 10,000 random pairs plus every
+    tile-edge pair exact in n11 and within 1e-5 bits, and the whole 4096 x 4096 output
+    bitwise symmetric."""
+    spec, X, cs_ref, pi, pj, ref = large_reference
+    n = spec.n
+    say(f"[parity] large 1000000x4096 epi={epi}")
+    out = torch.full((n, n), float("nan"), dtype=torch.float32, device=DEV)
+    n11 = torch.full((n, n), -1, dtype=torch.int32, device=DEV)
+    cs = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    mi.mi_all_pairs_ex(X, out=out, n11_out=n11, colsum_out=cs, epilogue=epi)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out.t()), "MI output is not bitwise symmetric"
+    assert torch.equal(n11, n11.t()), "n11 output is not symmetric"
+    assert bool(torch.isfinite(out).all()), "non-finite MI"
+    assert np.array_equal(cs.cpu().numpy().astype(np.int64), cs_ref), "column sums differ from the oracle"
+    ti, tj = torch.from_numpy(pi).to(DEV), torch.from_numpy(pj).to(DEV)
+    g11 = n11[ti, tj].cpu().numpy().astype(np.int64)
+    gmi = out[ti, tj].cpu().numpy().astype(np.float64)
+    bad = np.nonzero(g11 != ref["n11"])[0]
+    assert bad.size == 0, f"n11 differs at {bad.size} pairs, first ({pi[bad[0]]}, {pj[bad[0]]})"
+    err = np.abs(gmi - ref["mi"])
+    k = int(np.argmax(err))
+    assert err[k] <= MI_TOL, f"max |dMI| = {err[k]} at ({pi[k]}, {pj[k]})"
+    say(f"  {len(pi)} pairs + {n} column sums, max|dMI|={err[k]:.3e} at ({pi[k]}, {pj[k]})")
 
 
 @pytest.mark.parametrize("tile", [0, 1])

@@ -69,6 +69,37 @@ def test_oracle_pairs_matches_all_and_cells_sum_to_m():
     assert np.array_equal(np.diag(n11), c)
 
 
+def test_oracle_pairs_cells_pinned():
+    """n11, n10, n01, n00 of oracle.pairs one by one (golden hand counts, both orders, enumeration)."""
+    pins.check_cells(oracle.pairs)
+
+
+def test_oracle_transposed_layout_pinned():
+    """pairs_t / colsums_t (column-major input) against the cell pins and the row-major functions."""
+    pins.check_cells(lambda X, pi, pj: oracle.pairs_t(np.ascontiguousarray(X.T), pi, pj))
+    rng = np.random.default_rng(12)
+    X = (rng.random((1003, 37)) < rng.uniform(0.0, 0.8, size=37)).astype(np.uint8)
+    Xt = np.ascontiguousarray(X.T)
+    pi, pj = np.meshgrid(np.arange(37), np.arange(37), indexing="ij")
+    pi, pj = pi.ravel(), pj.ravel()
+    a, b = oracle.pairs(X, pi, pj), oracle.pairs_t(Xt, pi, pj)
+    for k in ("n11", "n10", "n01", "n00", "mi"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(oracle.colsums_t(Xt), X.sum(axis=0))
+    assert np.array_equal(oracle.colsums_t(Xt, n=20), oracle.colsums(X, n=20))
+
+
+def test_cell_pin_catches_swapped_off_diagonal_cells():
+    """A pair list that returns n10 and n01 swapped has the same MI (it is symmetric) and the
+    same n11; the cell pin must still fail on it."""
+    def swapped(X, pi, pj):
+        r = oracle.pairs(X, pi, pj)
+        r["n10"], r["n01"] = r["n01"], r["n10"]
+        return r
+    with pytest.raises(AssertionError):
+        pins.check_cells(swapped)
+
+
 def test_oracle_pitch_and_column_subset():
     rng = np.random.default_rng(6)
     full = (rng.random((100, 16)) < 0.4).astype(np.uint8)
