@@ -190,6 +190,34 @@ typedef enum mi_batch_mode {
 } mi_batch_mode;
 mi_status mi_all_pairs_batched(const mi_problem* probs, int64_t count, void* stream, int32_t mode);
 
+/* mi_all_pairs_ex for callers that cannot allocate device memory: code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipFree or other allocating routine.  Its scratch (the
+ * split-K workspace and the validation flag) is one fixed device array of
+ * 64 MiB + 256 bytes inside the library; each GPU the library runs on holds
+ * its own copy until the process ends, and the first call on a device clears
+ * it on `stream`.  The caller passes inputs and outputs as for
+ * mi_all_pairs_ex; the results are bitwise those of mi_all_pairs_ex with the
+ * same Gram, tile and splits.
+ * Differences from mi_all_pairs_ex:
+ *   - byte input runs the int8 Gram (MI_GRAM_AUTO included): there is no
+ *     scratch for the FP4 conversion, so MI_GRAM_FP4 with byte input is
+ *     MI_ERR_INVALID_ARG (pass MI_INPUT_FP4 input from mi_pack_fp4 instead);
+ *     bit and FP4 input follow mi_all_pairs_ex;
+ *   - X must be 16-byte aligned with ldx % 16 == 0 (no repack copy), else
+ *     MI_ERR_INVALID_ARG;
+ *   - algo must be MI_ALGO_DENSE, else MI_ERR_INVALID_ARG;
+ *   - a plan whose split-K workspace (tiles x (BT^2 + 2 BT + 1) x 4 bytes)
+ *     exceeds 64 MiB runs with the fewest splits instead (one, or what keeps
+ *     FP4 units at <= 2^24 rows); an explicit `splits` that does not fit, or
+ *     an FP4 problem whose minimum does not, is MI_ERR_INVALID_ARG.
+ * Every call on a device shares that device's array and leaves its workspace
+ * zeroed: calls that overlap on one GPU (other streams, other threads, graph
+ * replays running concurrently) race and give undefined results.  Calls
+ * ordered on one stream, or separated by synchronisation, do not.
+ * Asynchronous on `stream` unless validate is set. */
+mi_status mi_all_pairs_noalloc(const mi_problem* p, void* stream);
+
 /* Categorical variables: the extension to non-binary data that the paper's
  * Conclusions name as future work.  Column j of X holds codes
  * 0 .. levels[j] - 1, and MI runs over the whole joint value set (Eq. 1):

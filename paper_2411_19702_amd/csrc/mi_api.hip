@@ -295,12 +295,12 @@ bool converts_to_fp4(const mi_problem* p) {
 // each stage carries twice the rows: measured against unpacking to bytes for
 // the int8 Gram, 3.89 against 6.72 ms at 1,000,000 x 4,096, 0.113 against
 // 0.148 ms at 100,000 x 1,024, 0.176 against 0.205 ms at 2,000 x 8,192.
-static bool bits_to_fp4(const mi_problem* p) {
+bool bits_to_fp4(const mi_problem* p) {
   return p->packed == MI_INPUT_BITS && (p->gram == MI_GRAM_FP4 || (p->gram == MI_GRAM_AUTO && p->n >= 512));
 }
 
 // The problem runs the FP4 Gram.
-static bool runs_fp4(const mi_problem* p) {
+bool runs_fp4(const mi_problem* p) {
   return converts_to_fp4(p) || p->packed == MI_INPUT_FP4 || bits_to_fp4(p);
 }
 

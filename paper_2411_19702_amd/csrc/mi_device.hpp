@@ -97,7 +97,7 @@ struct ProbDev {
   int32_t* ws_n11;      // partial units: ntiles * BT * BT int32, all zero between calls
   int32_t* ws_col;      // partial units: ntiles * 2 * BT int32
   int32_t* counters;    // partial units: ntiles int32 (row steps arrived)
-  const int32_t* tiles; // tile order: ntiles entries of (I << 16) | J
+  const int32_t* tiles; // tile order: ntiles entries of (I << 16) | J; nullptr: decoded from the rank
   int32_t ntp;          // panels = ceil(n / BT)
   int32_t ntiles;       // ntp (ntp + 1) / 2
   int32_t ksteps;       // row steps of a whole tile = ceil(m / KT)
@@ -279,11 +279,60 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t stage_rsrc(uint64_t base, int 
   return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), 0, nrec, 0x00020000);
 }
 
-// Decode an upper-triangular tile from the order table.
+// Tiles (I, J), 0 <= I <= J < ntp, of the aligned square block with corner
+// (x0, y0) and side h: for each J of the block below ntp, the I of the block
+// up to J.
+__host__ __device__ inline int64_t tiles_in_block(int64_t x0, int64_t y0, int64_t h, int64_t ntp) {
+  const int64_t jlo = y0, jhi = (y0 + h < ntp ? y0 + h : ntp) - 1;
+  if (jhi < jlo) return 0;
+  int64_t c = 0;
+  // J in [x0, x0 + h - 2]: J - x0 + 1 tiles each.
+  const int64_t a = jlo > x0 ? jlo : x0, b = jhi < x0 + h - 2 ? jhi : x0 + h - 2;
+  if (a <= b) c += (b - a + 1) * (a + b - 2 * x0 + 2) / 2;
+  // J >= x0 + h - 1: the whole column of h tiles.
+  const int64_t d = jlo > x0 + h - 1 ? jlo : x0 + h - 1;
+  if (d <= jhi) c += h * (jhi - d + 1);
+  return c;
+}
+
+// The tile of rank t in the order of the tile table (upper-triangular tiles
+// sorted by the Morton code that puts bit b of I at position 2 b + 1 and bit
+// b of J at 2 b), without the table: descend the quadrant tree, whose
+// quadrants come in the order (I low, J low), (I low, J high), (I high, J
+// low), (I high, J high), skipping the tiles of the quadrants before the one
+// holding rank t.  At most 15 levels (ntp <= 32,767).
+__host__ __device__ inline void morton_tile(int ntp, int t, int& I, int& J) {
+  int64_t h = 1;
+  while (h < ntp) h <<= 1;
+  int64_t x0 = 0, y0 = 0, r = t;
+  while (h > 1) {
+    h >>= 1;
+    const int64_t c0 = tiles_in_block(x0, y0, h, ntp);
+    if (r < c0) continue;
+    r -= c0;
+    const int64_t c1 = tiles_in_block(x0, y0 + h, h, ntp);
+    if (r < c1) { y0 += h; continue; }
+    r -= c1;
+    const int64_t c2 = tiles_in_block(x0 + h, y0, h, ntp);
+    if (r < c2) { x0 += h; continue; }
+    r -= c2;
+    x0 += h;
+    y0 += h;
+  }
+  I = (int)x0;
+  J = (int)y0;
+}
+
+// Decode an upper-triangular tile from the order table, or from its rank
+// when the problem carries no table.
 __device__ __forceinline__ void tile_ij(const ProbDev& P, int t, int& I, int& J) {
-  const int v = P.tiles[t];
-  I = v >> 16;
-  J = v & 0xFFFF;
+  if (P.tiles) {
+    const int v = P.tiles[t];
+    I = v >> 16;
+    J = v & 0xFFFF;
+  } else {
+    morton_tile(P.ntp, t, I, J);
+  }
 }
 
 // LDS of one workgroup: the four ring slots are separate objects (so the

@@ -49,6 +49,10 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
 bool fp4_preferred(int64_t m, int64_t n);
 // Byte input that the dense path converts to FP4 first (requested, or the library's choice).
 bool converts_to_fp4(const mi_problem* p);
+// Bit input unpacked on chip to FP4 codes (requested, or the library's choice).
+bool bits_to_fp4(const mi_problem* p);
+// The problem runs the FP4 Gram (FP4 input, converted bytes or bits to FP4).
+bool runs_fp4(const mi_problem* p);
 // need_output: n > 0 needs out, n11_out or pairs (not for planning queries).
 mi_status check_problem(const mi_problem* p, int64_t* ldx_out, bool need_output = true);
 bool is_aligned(const uint8_t* X, int64_t ldx);

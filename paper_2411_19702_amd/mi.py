@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
         "mi_all_pairs_async": (i32, [vp, i64, i64, vp, vp]),
         "mi_all_pairs_ex": (i32, [P(mi_problem), vp]),
         "mi_all_pairs_batched": (i32, [P(mi_problem), i64, vp, i32]),
+        "mi_all_pairs_noalloc": (i32, [P(mi_problem), vp]),
         "mi_plan": (i32, [i64, i64, i64, P(i32), P(i32)]),
         "mi_tune": (i32, [i64, i64, i64, P(i32), P(i32), P(ctypes.c_double)]),
         "mi_tuner_save": (i32, [ctypes.c_char_p]),
@@ -274,6 +275,18 @@ def mi_all_pairs_ex(X: torch.Tensor, out: Optional[torch.Tensor] = None, n: Opti
         out = _new_out(X, n)
     p = make_problem(X, out, n=n, **kw)
     _check(lib().mi_all_pairs_ex(ctypes.byref(p), _stream_handle(stream)))
+    return out
+
+
+def mi_all_pairs_noalloc(X: torch.Tensor, out: Optional[torch.Tensor] = None, n: Optional[int] = None, stream=None,
+                         dense: bool = True, **kw) -> Optional[torch.Tensor]:
+    """mi_all_pairs_ex through the entry point that allocates no device memory
+    (the library's fixed scratch array; byte input on the int8 Gram).  out=None
+    allocates the n x n matrix here, in torch, unless dense=False."""
+    if out is None and dense:
+        out = _new_out(X, n)
+    p = make_problem(X, out, n=n, **kw)
+    _check(lib().mi_all_pairs_noalloc(ctypes.byref(p), _stream_handle(stream)))
     return out
 
 

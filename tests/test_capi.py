@@ -258,3 +258,19 @@ def test_column_limit(L):
     p.pairs, p.pairs_capacity, p.pairs_count, p.pairs_threshold = 64, 4, 128, 0.5
     assert L.mi_all_pairs_ex(ctypes.byref(p), None) == 1
     assert b"n must be" in L.mi_last_error()
+
+
+def test_noalloc_argument_checks(L):
+    """The no-allocation entry point: the checks of mi_all_pairs_ex, plus no
+    repack (aligned X and pitch only), no FP4 conversion of bytes and the dense
+    algorithm only, all before any device work."""
+    from paper_2411_19702_amd import mi
+    def na(**kw):
+        return L.mi_all_pairs_noalloc(ctypes.byref(_problem(mi, **{"X": 16, "out": 16, "ldx": 16, **kw})), None)
+    assert L.mi_all_pairs_noalloc(None, None) == 1
+    assert na(m=0) == 1 and na(ldx=3) == 1 and na(epilogue=5) == 1
+    assert na(X=17) == 1 and b"aligned" in L.mi_last_error()
+    assert na(ldx=24) == 1 and b"aligned" in L.mi_last_error()
+    assert na(gram=mi.MI_GRAM_FP4) == 1 and b"FP4" in L.mi_last_error()
+    assert na(algo=mi.MI_ALGO_SPARSE) == 1 and na(algo=mi.MI_ALGO_AUTO) == 1
+    assert na(n=0) == 0                                         # no-op, no device work
