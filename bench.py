@@ -421,6 +421,24 @@ def bench_batched(dev, reps: int = 3):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         res[name] = {"ms": dt * 1e3, "pair_updates_per_s": pu / dt}
+    # The batch autotuner on the same batch: its pick, then the persistent
+    # mode timed again under the tuned plan (heuristic timed above).
+    t0 = time.perf_counter()
+    tuned_ms, heur_ms = mi.mi_tune_batched(probs)
+    tune_s = time.perf_counter() - t0
+    tiles, splits = mi.mi_plan_batched(probs)
+    mi.mi_all_pairs_batched(probs, mode=mi.MI_BATCH_PERSISTENT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mi.mi_all_pairs_batched(probs, mode=mi.MI_BATCH_PERSISTENT)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    res["persistent_tuned"] = {"ms": dt * 1e3, "pair_updates_per_s": pu / dt, "tuner_ms": tuned_ms,
+                               "tuner_heuristic_ms": heur_ms, "tuning_s": tune_s,
+                               "tiles_256": tiles.count(mi.MI_TILE_256), "tiles_128": tiles.count(mi.MI_TILE_128),
+                               "units_splits_total": int(sum(splits))}
+    mi.mi_tuner_clear()
     del Xs, outs
     torch.cuda.empty_cache()
     return res

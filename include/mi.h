@@ -306,12 +306,38 @@ mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* spl
 /* Autotuner: time the candidate (tile, splits) configurations for this shape
  * on the current device, with the Gram the library would run for byte input
  * of this shape (FP4 from n >= 1536 and m n^2 >= 6e10, else int8), on a
- * scratch all-ones matrix in that layout (every split-K partial is then
- * published, the costly case), and remember the fastest for every later call
- * with the same shape class and Gram.  *best_ms receives its time (may be
- * NULL).  The tuner file holds one JSON line per entry; lines without the
- * "fp4" field are int8 entries. */
+ * scratch matrix in that layout holding a hashed 0/1 pattern of density 1/8,
+ * and remember the fastest for every later call with the same shape class
+ * and Gram.  Each candidate's time is the median of five launches after a
+ * warm-up; the library's heuristic plan is kept unless a candidate is at
+ * least 3% faster.  *best_ms receives the chosen plan's time (may be NULL).
+ * The tuner file holds one JSON line per entry; lines without the "fp4" field
+ * are int8 entries. */
 mi_status mi_tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms);
+
+/* Batch autotuner for the persistent mode of mi_all_pairs_batched: runs the
+ * caller's batch itself (its data and outputs; every run writes the same
+ * results) under candidate plans -- the tile of the datasets whose tile is
+ * left to the library (one 256- or 128-wide tile for all, or 128-wide below
+ * 512 / 1,024 columns and 256-wide above) and the K-split target (the batch's
+ * work over the persistent slots times 1, 2, 4, 8 or 16) -- and remembers
+ * the fastest for every later persistent call on a batch with the same
+ * signature (the multiset of the datasets' shape classes, as mi_tune's,
+ * layouts, Gram choices and explicit tile / split requests).  The
+ * library's heuristic plan is kept unless a candidate is at least 3% faster.
+ * Times are medians of five runs after a warm-up, on `stream`, which it
+ * synchronises.  *best_ms and *heuristic_ms (either may be NULL) receive the
+ * chosen and the heuristic plan's times.  Entries are saved and loaded with
+ * the tuner file ("batch" lines) and cleared by mi_tuner_clear. */
+mi_status mi_tune_batched(const mi_problem* probs, int64_t count, void* stream, double* best_ms,
+                          double* heuristic_ms);
+
+/* The plan the persistent mode would run for this batch (tuned or heuristic):
+ * per dataset, its tile (mi_tile; MI_TILE_AUTO for n == 0) and K-split count
+ * (0 for n == 0), into HOST arrays of `count` entries (either may be NULL).
+ * Checks the batch like mi_all_pairs_batched; launches nothing. */
+mi_status mi_plan_batched(const mi_problem* probs, int64_t count, int32_t* tiles, int32_t* splits);
+
 mi_status mi_tuner_save(const char* path);   /* JSON lines */
 mi_status mi_tuner_load(const char* path);
 void mi_tuner_clear(void);

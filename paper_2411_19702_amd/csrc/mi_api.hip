@@ -502,7 +502,111 @@ static std::string batch_key(const mi_problem* probs, int64_t count, const std::
   return k;
 }
 
-mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode) {
+
+// ------------------------------------------------------- persistent batches --
+// How a persistent batch is planned: the tile of the datasets whose tile is
+// left to the library, and the K-split target.
+//   tile kBatchTileAuto: one tile for all of them, 256-wide unless most of
+//        the work (m n^2) is in datasets narrower than 512 columns;
+//   MI_TILE_128 / MI_TILE_256: that tile for all of them;
+//   kBatchTileByWidth: 128-wide below narrow_n columns, 256-wide from there
+//        (two launches, one per tile).
+//   fdiv: each dataset is split so that no unit is much larger than the
+//        batch's MAC work over (persistent slots x fdiv); units of very
+//        different datasets then balance in the dynamic queue.
+// The heuristic is {kBatchTileAuto, 512, 4}; the batch tuner (mi_tune_batched)
+// times candidates on the caller's batch and stores the fastest under the
+// batch's signature.
+constexpr int kBatchTileAuto = 0, kBatchTileByWidth = 3;
+
+static BatchChoice heuristic_batch_choice() { return BatchChoice{kBatchTileAuto, 512, 4}; }
+
+// Batch signature: the multiset of the datasets' shape classes (the single
+// tuner's m and n classes), layouts, Gram choices and explicit tile / split
+// requests, hashed (FNV-1a, 64 bits) in sorted order.
+static uint64_t batch_signature(const mi_problem* probs, int64_t count, const std::vector<char>& aligned,
+                                const std::vector<char>& f4) {
+  std::vector<std::tuple<int, int, int, int, int, int, int>> keys;
+  keys.reserve(count);
+  for (int64_t d = 0; d < count; ++d) {
+    if (probs[d].n == 0) continue;
+    const ShapeKey k = shape_key(probs[d].m, probs[d].n, aligned[d] != 0, f4[d] != 0);
+    keys.emplace_back(k.mb, k.nb, k.aligned, k.fp4, probs[d].packed, probs[d].tile, probs[d].splits);
+  }
+  std::sort(keys.begin(), keys.end());
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int v) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= (uint64_t)((uint32_t)v >> (8 * b)) & 0xFFu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((int)keys.size());
+  for (const auto& k : keys) {
+    mix(std::get<0>(k)); mix(std::get<1>(k)); mix(std::get<2>(k)); mix(std::get<3>(k));
+    mix(std::get<4>(k)); mix(std::get<5>(k)); mix(std::get<6>(k));
+  }
+  return h;
+}
+
+static std::map<uint64_t, std::pair<BatchChoice, double>> g_batch_tuned;  // under g_tune_mu
+
+static BatchChoice batch_choice(const mi_problem* probs, int64_t count, const std::vector<char>& aligned,
+                                const std::vector<char>& f4) {
+  const uint64_t sig = batch_signature(probs, count, aligned, f4);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_batch_tuned.find(sig);
+  return it != g_batch_tuned.end() ? it->second.first : heuristic_batch_choice();
+}
+
+static mi_status plan_persistent(const mi_problem* probs, int64_t count, const std::vector<char>& aligned,
+                                 const std::vector<char>& conv, const std::vector<char>& f4, const BatchChoice& ch,
+                                 const DeviceInfo& di, std::vector<Plan>& plans) {
+  int batch_tile = ch.tile;
+  if (batch_tile == kBatchTileAuto) {
+    // In a shared work queue the 256-wide tiles measured faster even for
+    // small datasets (5.6 ms against 8.3 ms for the 256-dataset mix), so they
+    // are used unless most of the work is in datasets narrower than 512
+    // columns, which would mostly compute padding.
+    double wide = 0.0, narrow = 0.0;
+    for (int64_t d = 0; d < count; ++d) {
+      if (probs[d].n == 0 || probs[d].tile != MI_TILE_AUTO) continue;
+      const double w = (double)probs[d].m * (double)probs[d].n * (double)probs[d].n;
+      (probs[d].n >= 512 ? wide : narrow) += w;
+    }
+    batch_tile = wide >= narrow ? MI_TILE_256 : MI_TILE_128;
+  }
+  double total = 0.0;
+  for (int64_t d = 0; d < count; ++d) {
+    if (probs[d].n == 0) continue;
+    int tile = probs[d].tile;
+    if (tile == MI_TILE_AUTO)
+      tile = batch_tile == kBatchTileByWidth ? (probs[d].n < ch.narrow_n ? MI_TILE_128 : MI_TILE_256) : batch_tile;
+    Plan p0;
+    mi_status s = choose_plan(probs[d].m, probs[d].n, aligned[d] || conv[d], tile, 1, &p0, f4[d]);
+    if (s != MI_OK) return s;
+    total += (double)p0.ntiles * p0.bt * p0.bt * (double)probs[d].m;
+    plans[d] = p0;
+  }
+  const double slots = (double)di.cus * di.pocc[0][0];
+  const double target = std::max(total / (slots * std::max(ch.fdiv, 1)), 1.0);
+  for (int64_t d = 0; d < count; ++d) {
+    if (probs[d].n == 0) continue;
+    int sp = probs[d].splits;
+    if (sp <= 0) {
+      const double unit = (double)plans[d].bt * plans[d].bt * (double)probs[d].m;
+      sp = (int)std::min<double>(std::ceil(unit / target), std::max<int64_t>(1, probs[d].m / 1024));
+      sp = std::max(sp, 1);
+    }
+    plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].cfg, sp);
+    while (f4[d] && plans[d].kchunk > kFp4MaxUnitRows)  // exact FP32 counts
+      plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].cfg, plans[d].splits + 1);
+  }
+  return MI_OK;
+}
+
+mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode, const BatchChoice* choice,
+                      std::vector<Plan>* plans_out) {
   if (count < 0) return fail(MI_ERR_INVALID_ARG, "count < 0");
   if (count == 0) return MI_OK;
   if (!probs) return fail(MI_ERR_INVALID_ARG, "probs is NULL");
@@ -537,46 +641,9 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   for (int64_t d = 0; d < count; ++d) aligned[d] = is_aligned(probs[d].X, ldx[d]) ? 1 : 0;
 
   if (mode == MI_BATCH_PERSISTENT) {
-    // One tile configuration for every dataset whose tile is left to the
-    // library (one launch, one tail).  In a shared work queue the 256-wide
-    // tiles measured faster even for small datasets (5.6 ms against 8.3 ms
-    // for the 256-dataset mix), so they are used unless most of the work is
-    // in datasets narrower than 512 columns, which would mostly compute
-    // padding.
-    double wide = 0.0, narrow = 0.0;
-    for (int64_t d = 0; d < count; ++d) {
-      if (probs[d].n == 0 || probs[d].tile != MI_TILE_AUTO) continue;
-      const double w = (double)probs[d].m * (double)probs[d].n * (double)probs[d].n;
-      (probs[d].n >= 512 ? wide : narrow) += w;
-    }
-    const int batch_tile = wide >= narrow ? MI_TILE_256 : MI_TILE_128;
-    // Split each dataset's K range so that no unit is much larger than the
-    // average share of one persistent slot: units of very different datasets
-    // then balance in the dynamic queue.
-    double total = 0.0;
-    for (int64_t d = 0; d < count; ++d) {
-      if (probs[d].n == 0) continue;
-      Plan p0;
-      const int tile = probs[d].tile != MI_TILE_AUTO ? probs[d].tile : batch_tile;
-      s = choose_plan(probs[d].m, probs[d].n, aligned[d] || conv[d], tile, 1, &p0, f4[d]);
-      if (s != MI_OK) return s;
-      total += (double)p0.ntiles * p0.bt * p0.bt * (double)probs[d].m;
-      plans[d] = p0;
-    }
-    const double slots = (double)di.cus * di.pocc[0][0];
-    const double target = std::max(total / (slots * 4.0), 1.0);
-    for (int64_t d = 0; d < count; ++d) {
-      if (probs[d].n == 0) continue;
-      int sp = probs[d].splits;
-      if (sp <= 0) {
-        const double unit = (double)plans[d].bt * plans[d].bt * (double)probs[d].m;
-        sp = (int)std::min<double>(std::ceil(unit / target), std::max<int64_t>(1, probs[d].m / 1024));
-        sp = std::max(sp, 1);
-      }
-      plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].cfg, sp);
-      while (f4[d] && plans[d].kchunk > kFp4MaxUnitRows)  // exact FP32 counts
-        plans[d] = make_plan(probs[d].m, probs[d].n, plans[d].cfg, plans[d].splits + 1);
-    }
+    BatchChoice ch = choice ? *choice : batch_choice(probs, count, aligned, f4);
+    s = plan_persistent(probs, count, aligned, conv, f4, ch, di, plans);
+    if (s != MI_OK) return s;
   } else {
     for (int64_t d = 0; d < count; ++d) {
       if (probs[d].n == 0) continue;
@@ -584,6 +651,10 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
                       f4[d]);
       if (s != MI_OK) return s;
     }
+  }
+  if (plans_out) {  // planning query: nothing launched
+    *plans_out = plans;
+    return MI_OK;
   }
 
   // One split-K workspace and one buffer for the repacked and converted
@@ -817,9 +888,9 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   if (s != MI_OK) return s;
   // The Gram the library would run for byte input of this shape.  Unaligned
   // layouts are repacked (int8) or converted (FP4) to a 16-byte pitch first,
-  // so time on a matrix of that pitch.  It is all ones (bytes 1, or FP4
-  // codes 0b0010 in every nibble): every count is nonzero, so every split-K
-  // partial is published (the kernels skip zero partials), the costly case.
+  // so time on a matrix of that pitch.  It holds a hashed 0/1 pattern of
+  // density 1/8 (the kernels' time depends on the data only through the
+  // split-K partials they skip when zero, which are then rare).
   const bool fp4 = fp4_preferred(m, n);
   const bool aligned = ldx % 16 == 0;
   const int64_t ld = fp4 ? packed_pitch((n + 1) / 2) : (aligned ? ldx : packed_pitch(n));
@@ -839,46 +910,62 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   hipEvent_t e0 = nullptr, e1 = nullptr;
   Tuned best{-1, 0, 1e30};
   auto body = [&]() -> mi_status {
-    HIPCHK(hipMemset(X, fp4 ? 0x22 : 1, xbytes));
     HIPCHK(hipStreamCreate(&st));
+    HIPCHK(launch_fill_pattern(X, m, ld, fp4 ? (n + 1) / 2 : n, fp4, st));
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     hipError_t te;
+    // Median of five launches after a warm-up.
+    auto time_plan = [&](const Plan& pl, double* ms_out) -> mi_status {
+      const int32_t* tiles = tile_table(pl.ntp, &te);
+      if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(te));
+      void* ws = nullptr;
+      mi_status ss = workspace(st, 0, workspace_bytes(pl), &ws);
+      if (ss != MI_OK) return ss;
+      mi_problem pr;
+      mi_problem_init(&pr, X, m, n, out);
+      pr.ldx = ld;
+      pr.packed = fp4 ? MI_INPUT_FP4 : MI_INPUT_BYTES;
+      const ProbDev P = make_probdev(&pr, X, ld, pl, ws, tiles);
+      HIPCHK(launch_plain(pl.cfg, P, st));  // warm-up
+      std::vector<float> ts;
+      for (int rep = 0; rep < 5; ++rep) {
+        HIPCHK(hipEventRecord(e0, st));
+        HIPCHK(launch_plain(pl.cfg, P, st));
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ts.push_back(ms);
+      }
+      std::sort(ts.begin(), ts.end());
+      *ms_out = ts[ts.size() / 2];
+      return MI_OK;
+    };
+    // The heuristic plan first: another candidate replaces it only when at
+    // least 3% faster, so timing noise cannot make a tuned plan slower.
+    const int hcfg = heuristic_cfg(m, n);
+    Plan hp = make_plan(m, n, hcfg, heuristic_splits(m, make_plan(m, n, hcfg, 1), di.cus, fp4 ? 2.0 : 1.0));
+    while (fp4 && hp.kchunk > kFp4MaxUnitRows) hp = make_plan(m, n, hcfg, hp.splits + 1);
+    double heur = 0.0;
+    mi_status hs = time_plan(hp, &heur);
+    if (hs != MI_OK) return hs;
+    best = Tuned{hp.cfg, hp.splits, heur};
     for (int cfg = 0; cfg < kNumCfg; ++cfg) {
       const Plan p1 = make_plan(m, n, cfg, 1);
       std::vector<int> cands;
       for (int sp = 1; sp <= 16; ++sp) cands.push_back(sp);
       for (int sp : {20, 24, 32, 48, 64, 96, 128, 192, 256}) cands.push_back(sp);
-      cands.push_back(heuristic_splits(m, p1, di.cus, fp4 ? 2.0 : 1.0));
-      std::sort(cands.begin(), cands.end());
-      cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
-      const int32_t* tiles = tile_table(p1.ntp, &te);
-      if (!tiles) return fail(MI_ERR_DEVICE, "tile table: %s", hipGetErrorString(te));
       for (int sp : cands) {
         if (sp > p1.ksteps) continue;
         const Plan pl = make_plan(m, n, cfg, sp);
         if (pl.splits != sp || (double)pl.ntiles * pl.splits > 4.0e6) continue;
         if (fp4 && pl.kchunk > kFp4MaxUnitRows) continue;  // FP32 counts exact per unit
-        void* ws = nullptr;
-        mi_status ss = workspace(st, 0, workspace_bytes(pl), &ws);
+        if (cfg == hp.cfg && sp == hp.splits) continue;    // the heuristic, timed above
+        double ms = 0.0;
+        mi_status ss = time_plan(pl, &ms);
         if (ss != MI_OK) return ss;
-        mi_problem pr;
-        mi_problem_init(&pr, X, m, n, out);
-        pr.ldx = ld;
-        pr.packed = fp4 ? MI_INPUT_FP4 : MI_INPUT_BYTES;
-        const ProbDev P = make_probdev(&pr, X, ld, pl, ws, tiles);
-        HIPCHK(launch_plain(cfg, P, st));  // warm-up
-        float best_here = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-          HIPCHK(hipEventRecord(e0, st));
-          HIPCHK(launch_plain(cfg, P, st));
-          HIPCHK(hipEventRecord(e1, st));
-          HIPCHK(hipEventSynchronize(e1));
-          float ms = 0.f;
-          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-          best_here = std::min(best_here, ms);
-        }
-        if (best_here < best.ms) best = Tuned{cfg, pl.splits, best_here};
+        if (ms < 0.97 * heur && ms < best.ms) best = Tuned{cfg, pl.splits, ms};
       }
     }
     return MI_OK;
@@ -905,6 +992,79 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   return MI_OK;
 }
 
+// Batch tuner: time the persistent mode of the caller's own batch (its data,
+// its outputs, which every candidate overwrites with the same results) under
+// candidate plans, and keep the fastest under the batch's signature.  The
+// heuristic is kept unless a candidate is at least 3% faster (medians of five
+// runs after one warm-up).
+mi_status tune_batched(const mi_problem* probs, int64_t count, hipStream_t st, double* best_ms, double* heur_ms,
+                       BatchChoice* chosen) {
+  std::vector<Plan> plans;
+  mi_status s = run_batched(probs, count, st, MI_BATCH_PERSISTENT, nullptr, &plans);  // checks the batch
+  if (s != MI_OK) return s;
+  std::vector<char> aligned(count), f4(count);
+  for (int64_t d = 0; d < count; ++d) {
+    int64_t ldx = 0;
+    s = check_problem(&probs[d], &ldx);
+    if (s != MI_OK) return s;
+    aligned[d] = is_aligned(probs[d].X, ldx) ? 1 : 0;
+    f4[d] = runs_fp4(&probs[d]) ? 1 : 0;
+  }
+  std::vector<BatchChoice> cands;
+  cands.push_back(heuristic_batch_choice());
+  const std::pair<int, int> tiles[] = {{kBatchTileAuto, 512},    {(int)MI_TILE_128, 512}, {(int)MI_TILE_256, 512},
+                                       {kBatchTileByWidth, 512}, {kBatchTileByWidth, 1024}};
+  for (const auto& tn : tiles)
+    for (int fdiv : {1, 2, 4, 8, 16}) {
+      const BatchChoice c{tn.first, tn.second, fdiv};
+      if (c.tile == kBatchTileAuto && c.fdiv == 4) continue;  // the heuristic, already first
+      cands.push_back(c);
+    }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double best = 1e30, heur = 1e30;
+  BatchChoice best_c = heuristic_batch_choice();
+  auto body = [&]() -> mi_status {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      mi_status r = run_batched(probs, count, st, MI_BATCH_PERSISTENT, &cands[ci]);  // warm-up
+      if (r != MI_OK) return r;
+      std::vector<float> ts;
+      for (int rep = 0; rep < 5; ++rep) {
+        HIPCHK(hipEventRecord(e0, st));
+        r = run_batched(probs, count, st, MI_BATCH_PERSISTENT, &cands[ci]);
+        if (r != MI_OK) return r;
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ts.push_back(ms);
+      }
+      std::sort(ts.begin(), ts.end());
+      const double med = ts[ts.size() / 2];
+      if (ci == 0) {
+        heur = best = med;
+      } else if (med < 0.97 * heur && med < best) {
+        best = med;
+        best_c = cands[ci];
+      }
+    }
+    return MI_OK;
+  };
+  s = body();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s != MI_OK) return s;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_batch_tuned[batch_signature(probs, count, aligned, f4)] = {best_c, best};
+  }
+  if (best_ms) *best_ms = best;
+  if (heur_ms) *heur_ms = heur;
+  if (chosen) *chosen = best_c;
+  return MI_OK;
+}
+
 mi_status tuner_save(const char* path) {
   if (!path) return fail(MI_ERR_INVALID_ARG, "path is NULL");
   FILE* f = fopen(path, "w");
@@ -914,6 +1074,10 @@ mi_status tuner_save(const char* path) {
     fprintf(f, "{\"mb\": %d, \"nb\": %d, \"aligned\": %d, \"tile\": %d, \"splits\": %d, \"ms\": %.6f, \"fp4\": %d}\n",
             kv.first.mb, kv.first.nb, kv.first.aligned, cfg_tile(kv.second.cfg), kv.second.splits, kv.second.ms,
             kv.first.fp4);
+  for (auto& kv : g_batch_tuned)
+    fprintf(f, "{\"batch\": \"%016llx\", \"tile\": %d, \"narrow\": %d, \"fdiv\": %d, \"ms\": %.6f}\n",
+            (unsigned long long)kv.first, kv.second.first.tile, kv.second.first.narrow_n, kv.second.first.fdiv,
+            kv.second.second);
   fclose(f);
   return MI_OK;
 }
@@ -926,6 +1090,17 @@ mi_status tuner_load(const char* path) {
   int nread = 0;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   while (fgets(line, sizeof line, f)) {
+    unsigned long long sig = 0;
+    BatchChoice bc;
+    double bms = 0.0;
+    if (sscanf(line, " {\"batch\": \"%16llx\", \"tile\": %d, \"narrow\": %d, \"fdiv\": %d, \"ms\": %lf}", &sig, &bc.tile,
+               &bc.narrow_n, &bc.fdiv, &bms) == 5) {
+      if (bc.tile >= 0 && bc.tile <= kBatchTileByWidth && bc.narrow_n >= 1 && bc.fdiv >= 1 && bc.fdiv <= 1024) {
+        g_batch_tuned[(uint64_t)sig] = {bc, bms};
+        ++nread;
+      }
+      continue;
+    }
     ShapeKey k;
     Tuned t;
     int tile = 0;
@@ -946,6 +1121,7 @@ mi_status tuner_load(const char* path) {
 void tuner_clear() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned.clear();
+  g_batch_tuned.clear();
 }
 
 }  // namespace mi
@@ -1048,6 +1224,25 @@ mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* spl
 mi_status mi_tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits, double* best_ms) {
   clear_error();
   return tune(m, n, ldx, tile, splits, best_ms);
+}
+
+mi_status mi_tune_batched(const mi_problem* probs, int64_t count, void* stream, double* best_ms,
+                          double* heuristic_ms) {
+  clear_error();
+  return tune_batched(probs, count, (hipStream_t)stream, best_ms, heuristic_ms, nullptr);
+}
+
+mi_status mi_plan_batched(const mi_problem* probs, int64_t count, int32_t* tiles, int32_t* splits) {
+  clear_error();
+  std::vector<Plan> plans;
+  mi_status s = run_batched(probs, count, nullptr, MI_BATCH_PERSISTENT, nullptr, &plans);
+  if (s != MI_OK) return s;
+  for (int64_t d = 0; d < count; ++d) {
+    const bool empty = probs[d].n == 0;
+    if (tiles) tiles[d] = empty ? MI_TILE_AUTO : (plans[d].cfg == 1 ? MI_TILE_256 : MI_TILE_128);
+    if (splits) splits[d] = empty ? 0 : plans[d].splits;
+  }
+  return MI_OK;
 }
 
 mi_status mi_tuner_save(const char* path) {

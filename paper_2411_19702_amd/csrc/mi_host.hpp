@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "mi.h"
 #include "mi_internal.hpp"
 
@@ -68,6 +70,15 @@ mi_status run_one(const mi_problem* p, hipStream_t st, int ws_slot, bool upper_o
 mi_status run_sparse(const mi_problem* p, int64_t ldx, hipStream_t st, bool auto_choice, bool* used);
 void release_scratch_of(hipStream_t st);
 void release_stream_resources(hipStream_t st);  // scratch and batch descriptors of a stream
-mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode);
+// A persistent batch's plan (see plan_persistent in mi_api.hip).
+struct BatchChoice {
+  int tile = 0;        // 0: one tile by the work's majority width; MI_TILE_128 / _256; 3: by dataset width
+  int narrow_n = 512;  // tile 3: datasets narrower than this take 128-wide tiles
+  int fdiv = 4;        // K-split target: the batch's work over (persistent slots x fdiv)
+};
+// choice: the persistent mode's plan (nullptr: the tuned one for this batch, else the heuristic).
+// plans_out: planning query (checks and plans only, nothing launched or allocated).
+mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode,
+                      const BatchChoice* choice = nullptr, std::vector<Plan>* plans_out = nullptr);
 
 }  // namespace mi

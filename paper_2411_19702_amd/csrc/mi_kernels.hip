@@ -332,6 +332,35 @@ hipError_t launch_persistent(int cfg, bool fp4, const ProbDev* probs, const Unit
   return hipGetLastError();
 }
 
+// Tuner input: a 0/1 pattern of about 1/8 density from a 32-bit integer
+// hash of the entry's position (bytes 1, or the FP4 code 0b0010 per nibble);
+// bytes of a row past `bytes` are 0.
+__global__ __launch_bounds__(256) void k_fill_pattern(uint8_t* __restrict__ X, int64_t m, int64_t ld, int64_t bytes,
+                                                      int32_t fp4) {
+  const int64_t total = m * ld;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
+    const int64_t row = q / ld, c = q - row * ld;
+    uint32_t v = 0;
+    if (c < bytes) {
+      uint32_t h = (uint32_t)(row * 0x9E3779B1u) ^ (uint32_t)(c * 0x85EBCA77u);
+      h ^= h >> 15;
+      h *= 0x2C1B3C6Du;
+      h ^= h >> 12;
+      h *= 0x297A2D39u;
+      h ^= h >> 15;
+      v = fp4 ? ((((h & 7u) == 0u) ? 0x02u : 0u) | ((((h >> 3) & 7u) == 0u) ? 0x20u : 0u)) : ((h & 7u) == 0u ? 1u : 0u);
+    }
+    X[q] = (uint8_t)v;
+  }
+}
+
+hipError_t launch_fill_pattern(uint8_t* X, int64_t m, int64_t ld, int64_t bytes, bool fp4, hipStream_t st) {
+  const int64_t chunks = (m * ld + 255) / 256;
+  const int64_t blocks = chunks < 65536 ? (chunks > 0 ? chunks : 1) : 65536;
+  hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)blocks), dim3(256), 0, st, X, m, ld, bytes, fp4 ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, flag, 0, 1);
   const int64_t blocks = m < 4096 ? m : 4096;

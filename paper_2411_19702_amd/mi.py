@@ -118,6 +118,8 @@ def lib() -> ctypes.CDLL:
         "mi_all_pairs_noalloc": (i32, [P(mi_problem), vp]),
         "mi_plan": (i32, [i64, i64, i64, P(i32), P(i32)]),
         "mi_tune": (i32, [i64, i64, i64, P(i32), P(i32), P(ctypes.c_double)]),
+        "mi_tune_batched": (i32, [P(mi_problem), i64, vp, P(ctypes.c_double), P(ctypes.c_double)]),
+        "mi_plan_batched": (i32, [P(mi_problem), i64, vp, vp]),
         "mi_tuner_save": (i32, [ctypes.c_char_p]),
         "mi_tuner_load": (i32, [ctypes.c_char_p]),
         "mi_tuner_clear": (None, []),
@@ -314,6 +316,23 @@ def mi_tune(m: int, n: int, ldx: int = 0) -> Tuple[int, int, float]:
     t, s, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     _check(lib().mi_tune(m, n, ldx, ctypes.byref(t), ctypes.byref(s), ctypes.byref(ms)))
     return t.value, s.value, ms.value
+
+
+def mi_tune_batched(problems: Sequence[mi_problem], stream=None) -> Tuple[float, float]:
+    """Tune the persistent plan of this batch on its own data; returns (chosen ms, heuristic ms)."""
+    arr = (mi_problem * len(problems))(*problems)
+    best, heur = ctypes.c_double(), ctypes.c_double()
+    _check(lib().mi_tune_batched(arr, len(problems), _stream_handle(stream), ctypes.byref(best), ctypes.byref(heur)))
+    return best.value, heur.value
+
+
+def mi_plan_batched(problems: Sequence[mi_problem]) -> Tuple[List[int], List[int]]:
+    """(tiles, splits) per dataset of the persistent mode's plan for this batch."""
+    k = len(problems)
+    arr = (mi_problem * k)(*problems)
+    tiles, splits = (ctypes.c_int32 * max(k, 1))(), (ctypes.c_int32 * max(k, 1))()
+    _check(lib().mi_plan_batched(arr, k, ctypes.cast(tiles, ctypes.c_void_p), ctypes.cast(splits, ctypes.c_void_p)))
+    return list(tiles)[:k], list(splits)[:k]
 
 
 def mi_tuner_save(path: str) -> None:

@@ -46,3 +46,64 @@ def test_tuner_file_round_trip(tmp_path):
     mi.mi_tuner_clear()
     mi.mi_tuner_load(path)
     assert mi.mi_plan_ex(X)[:2] == (tile, splits)
+
+
+def _batch(count, m_range, n_range, seed=33):
+    from tests.test_gpu_batched import _alloc, _problems
+    specs = synth.specs_batched(seed=seed, count=count, m_range=m_range, n_range=n_range)
+    Xs = [synth.generate(s, device=DEV) for s in specs]
+    outs, n11s, css = _alloc(specs)
+    return specs, Xs, (outs, n11s, css), _problems(Xs, outs, n11s, css)
+
+
+def test_batch_tuner_entry_changes_the_persistent_plan_not_the_results(tmp_path):
+    """A batch entry (loaded from a tuner file) changes the persistent mode's
+    tiles and splits; the outputs stay bitwise those of the heuristic plan."""
+    specs, Xs, bufs, probs = _batch(24, (500, 20000), (64, 900))
+    say(f"[tune batched] {len(specs)} datasets: entry from a file")
+    tiles0, splits0 = mi.mi_plan_batched(probs)
+    mi.mi_all_pairs_batched(probs, mode=mi.MI_BATCH_PERSISTENT)
+    torch.cuda.synchronize()
+    ref = [[t.clone() for t in ts] for ts in bufs]
+    # Tune, then rewrite the stored entry to a different plan and load it back.
+    best, heur = mi.mi_tune_batched(probs)
+    assert 0 < best <= heur < 1e4
+    path = tmp_path / "tuned.jsonl"
+    mi.mi_tuner_save(str(path))
+    lines = [ln for ln in path.read_text().splitlines() if '"batch"' in ln]
+    assert len(lines) == 1
+    forced = tiles0.count(mi.MI_TILE_256) >= tiles0.count(mi.MI_TILE_128)
+    tile_code = mi.MI_TILE_128 if forced else mi.MI_TILE_256
+    sig = lines[0].split('"batch": "')[1].split('"')[0]
+    path.write_text('{"batch": "%s", "tile": %d, "narrow": 512, "fdiv": 16, "ms": 1.0}\n' % (sig, tile_code))
+    mi.mi_tuner_clear()
+    assert mi.mi_plan_batched(probs) == (tiles0, splits0)       # cleared: the heuristic again
+    mi.mi_tuner_load(str(path))
+    tiles1, splits1 = mi.mi_plan_batched(probs)
+    want = [mi.MI_TILE_128 if forced else mi.MI_TILE_256] * len(specs)
+    assert tiles1 == want and tiles1 != tiles0
+    assert sum(splits1) >= sum(splits0)                         # a finer split target
+    for ts in bufs:
+        for t in ts:
+            t.fill_(-7)
+    mi.mi_all_pairs_batched(probs, mode=mi.MI_BATCH_PERSISTENT)
+    torch.cuda.synchronize()
+    for k in range(3):
+        for a, b in zip(bufs[k], ref[k]):
+            assert torch.equal(a, b), "tuned persistent plan changed the outputs"
+
+
+def test_batch_tuner_on_a_mixed_batch_is_no_slower_than_the_heuristic():
+    specs, Xs, bufs, probs = _batch(48, (500, 50000), (64, 2048), seed=34)
+    say(f"[tune batched] {len(specs)} datasets: tuned vs heuristic")
+    best, heur = mi.mi_tune_batched(probs)
+    assert best <= heur
+    tiles, splits = mi.mi_plan_batched(probs)
+    assert all(t in (mi.MI_TILE_128, mi.MI_TILE_256) for t in tiles) and all(s >= 1 for s in splits)
+    mi.mi_all_pairs_batched(probs, mode=mi.MI_BATCH_PERSISTENT)
+    torch.cuda.synchronize()
+    from tests.test_gpu_batched import _run
+    seq = _run(specs, Xs, mi.MI_BATCH_SEQUENTIAL)
+    for k in range(3):
+        for a, b in zip(bufs[k], seq[k]):
+            assert torch.equal(a, b)
