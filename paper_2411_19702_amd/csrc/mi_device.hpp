@@ -42,6 +42,7 @@ typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 #define MI_LDS __attribute__((address_space(3)))
 
 constexpr int KT = 64;  // samples per stage = one MFMA K step
@@ -72,13 +73,9 @@ struct Cfg {
   static constexpr int RB4 = BT / 2;                    // FP4 layout: bytes of one panel row
   static constexpr int ROWS_PER_REGION4 = 1024 / RB4;
   static constexpr int SEGS4 = RB4 / 16;
-  static constexpr int STRIP = 32 * WTN;                // epilogue strip elements per wave
-  static constexpr int STRIP_BYTES = 2 * STRIP * 4;     // int32 counts + FP32 MI of a strip
-  static constexpr int WAVES_PER_SLOT = STAGE / STRIP_BYTES;
   static_assert(NS == 4, "the K loop is unrolled over four ring slots");
   static_assert(KT4 * RB4 == PANEL, "an FP4 stage holds as many bytes as a byte stage");
   static_assert(REGIONS % NWAVES == 0, "DMA regions must split evenly over waves");
-  static_assert(WAVES_PER_SLOT >= 1 && NWAVES <= NS * WAVES_PER_SLOT, "epilogue strips must fit in the ring");
 };
 using Cfg128 = Cfg<128, 2, 2, 4>;  // 4 waves of 64 x 64; 65 KB LDS, 2 workgroups per CU
 using Cfg256 = Cfg<256, 2, 4, 4>;  // 8 waves of 128 x 64; 130 KB LDS, 1 workgroup per CU
@@ -153,6 +150,11 @@ __device__ __forceinline__ float mi_value64(int m, int ci, int cj, int n11) {
   const double d01 = cell64(n01, ni0, cj, m);
   return (float)(((d11 + d00) + (d10 + d01)) / (double)m);
 }
+
+// The FP64 evaluation as a call: the unrolled epilogue evaluates 64-128
+// elements per wave, and inlining the FP64 logarithms at each would blow up
+// the code of the FP32 + fallback and FP64 modes.
+static __device__ __noinline__ float mi_value64_call(int m, int ci, int cj, int n11) { return mi_value64(m, ci, cj, n11); }
 
 // FP32 MI of one pair (Eq. 2 / 3).  a1i = m / c_i and a0i = m / (m - c_i)
 // for the row variable, r1j = 1 / c_j and r0j = 1 / (m - c_j) for the column
@@ -865,11 +867,12 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     __syncthreads();
   }
 
-  // Epilogue: derived cells, MI, tile and mirror write-back.  Each wave moves
-  // its accumulators through LDS (the ring is free now) one 32-row strip at a
-  // time: pass 1 reads the strip row-wise, evaluates MI once per element and
-  // writes the tile rows (consecutive lanes, consecutive j); pass 2 reads the
-  // strip column-wise and writes the mirror rows (consecutive i).
+  // Epilogue: derived cells, MI, tile and mirror write-back, straight from
+  // the accumulator registers.  In a 32 x 32 accumulator block, register r of
+  // lane l holds the count of tile row 8 (r / 4) + 4 (l / 32) + r % 4 and
+  // column l % 32: one register is two 32-column half rows (128-byte stores),
+  // and a lane's registers 4 g .. 4 g + 3 are four consecutive rows of one
+  // column (one 16-byte store into the mirror row of that column).
   const int n = P.n;
   const int64_t ln = n;
   if (diag && P.colsum_out) {
@@ -898,137 +901,185 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     }
   }
   __syncthreads();
-  constexpr int WTN = C::WTN;
-  constexpr int STRIP = C::STRIP;
-  static_assert(WTN == 64, "the strip loop gives each lane one column");
-  const int ws = wave / C::WAVES_PER_SLOT;  // selects, not an indexed array (keeps it out of memory)
-  uint8_t* strip_slot = ws == 0 ? sm.slot[0] : (ws == 1 ? sm.slot[1] : (ws == 2 ? sm.slot[2] : sm.slot[3]));
-  int32_t* sN = reinterpret_cast<int32_t*>(strip_slot + (wave % C::WAVES_PER_SLOT) * C::STRIP_BYTES);
-  float* sM = reinterpret_cast<float*>(sN + STRIP);
-  const int ibase = I * BT + wm * C::WTM;
-  const int jbase = J * BT + wn * WTN;
-  const int jl = wn * WTN + lane, j = jbase + lane;  // this lane's column
-  const int cj = sColB[jl];
-  const float r1j = rB1[jl], r0j = rB0[jl];
-  // Accumulator block a into the strip.  The strip loop below is not
-  // unrolled (its body, with the FP64 path, is large), so the block is picked
-  // by a switch whose cases index the accumulators with constants: they stay
-  // in registers.
-  auto put_strip = [&](auto A) {
-    constexpr int a = decltype(A)::value;
+  const int ibase = I * BT + wm * C::WTM;  // first row and column of this wave's block
+  const int jbase = J * BT + wn * C::WTN;
+  if (ibase >= n || jbase >= n) return;  // the wave's block lies in tile padding (uniform)
+  // Column factors of this lane's column in each fragment column block.
+  int cjb[FN];
+  float r1b[FN], r0b[FN];
 #pragma unroll
-    for (int b = 0; b < FN; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        sN[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * WTN + blk_b(b) * 32 + (lane & 31)] = acc[a][b][r];
-  };
-  // MI of the strip's rows, one column per lane, written as tile rows
-  // (consecutive lanes, consecutive j).  The epilogue mode is a template
-  // argument, so the FP32 loop carries no per-element mode tests.  In a
-  // diagonal tile only i <= j is stored; the mirror pass fills i > j, so the
-  // output is bitwise symmetric by construction.
-  auto strip_rows = [&](int i0, auto EPI) {
+  for (int b = 0; b < FN; ++b) {
+    const int jl = wn * C::WTN + blk_b(b) * 32 + (lane & 31);
+    cjb[b] = sColB[jl];
+    r1b[b] = rB1[jl];
+    r0b[b] = rB0[jl];
+  }
+  // Addresses: a wave-uniform 64-bit base per group of rows plus this lane's
+  // 32-bit byte offset (tile rows: row 4 (lane / 32), column lane % 32;
+  // mirror rows: row lane % 32, column 4 (lane / 32)).  The offsets stay
+  // below 2^32 for n below 2^25.
+  const uint32_t lane_tile = (uint32_t)(((lane >> 5) * 4) * n + (lane & 31)) * 4u;
+  const uint32_t lane_mir = (uint32_t)((lane & 31) * n + (lane >> 5) * 4) * 4u;
+  const uint32_t row_bytes = (uint32_t)n * 4u;
+  // Mirror stores of four consecutive rows as one 16-byte store need 16-byte
+  // aligned outputs and n % 4 == 0.
+  const bool vec = (n & 3) == 0 && ((uintptr_t)P.out & 15) == 0 && ((uintptr_t)P.n11_out & 15) == 0;
+  // A block strictly above the diagonal (every j > i) and inside the matrix
+  // stores without per-element tests.
+  const bool full = ibase + C::WTM <= n && jbase + C::WTN <= n && jbase >= ibase + C::WTM && vec;
+  const bool mirror = !P.upper_only && (P.out || P.n11_out);
+  // Evaluate and store accumulator block rows [A0, A0 + 2).  The epilogue
+  // mode and the block test are template arguments, so the FP32 path carries
+  // neither mode tests nor bounds tests; the sparse output goes with the
+  // tested path only.  A scheduling barrier after each group of four rows
+  // keeps the compiler from hoisting later groups' loads and arithmetic,
+  // whose registers on top of the live accumulators would spill.
+  auto emit_rows = [&](auto A0, auto EPI, auto FULL) {
     constexpr int epi = decltype(EPI)::value;
-    const int rows = min(32, n - i0);  // rows past n (tile padding) are skipped
-    // The count and MI of row rr (this lane's column).
-    auto eval = [&](int rr, int& v11, float& v) {
-      const int il = i0 - I * BT + rr;
-      v11 = sN[rr * WTN + lane];
-      const int ci = sColA[il];
-      if (epi == kEpiCounts) {
-        v = 0.0f;
-      } else if (epi == 2) {
-        v = mi_value64(P.m, ci, cj, v11);
-      } else {
-        v = mi_value32(P.m, ci, cj, v11, rA1[il], rA0[il], r1j, r0j, rfm);
-        if (epi == 1 && v < P.tau) v = mi_value64(P.m, ci, cj, v11);
-      }
-    };
-    // Its strip entry (for the mirror pass), tile-row stores and sparse output.
-    auto emit = [&](int rr, int v11, float v) {
-      const int i = i0 + rr;  // row, the same for all lanes
-      sM[rr * WTN + lane] = v;
-      if (i < n && j < n && (!diag || j >= i)) {
-        if (P.out) P.out[i * ln + j] = v;
-        if (P.n11_out) P.n11_out[i * ln + j] = v11;
-      }
-      if (P.pairs) {
-        // Sparse output: one atomic per wave and row, lanes in order.
-        const bool q = i < n && j < n && j > i && v >= P.thr;
-        const unsigned long long mask = __ballot(q);
-        if (mask) {  // uniform
-          const int leader = __ffsll((long long)mask) - 1;
-          unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(P.pairs_count, (unsigned long long)__popcll(mask));
-          base = __shfl(base, leader);
-          if (q) {
-            const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
-            if (idx < (unsigned long long)P.pairs_cap) {
-              int32_t* e3 = P.pairs + 3 * idx;
-              e3[0] = i;
-              e3[1] = j;
-              e3[2] = __float_as_int(v);
+    constexpr bool fast = decltype(FULL)::value;
+#pragma unroll
+    for (int a = decltype(A0)::value; a < decltype(A0)::value + 2 && a < FM; ++a) {
+      if (ibase + blk_a(a) * 32 >= n) continue;  // block rows past n (uniform)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int il = wm * C::WTM + blk_a(a) * 32 + g * 8;  // tile row of lane 0's register 4 g
+        const int row0 = I * BT + il;
+        const int i0 = row0 + (lane >> 5) * 4;               // this lane's row of register 4 g
+        const int ill = il + (lane >> 5) * 4;
+        const v4f a1 = *(const MI_LDS v4f*)(const MI_LDS float*)(rA1 + ill);
+        const v4f a0 = *(const MI_LDS v4f*)(const MI_LDS float*)(rA0 + ill);
+        const v4i ci = *(const MI_LDS v4i*)(const MI_LDS int32_t*)(sColA + ill);
+        const int64_t tile_el = (int64_t)row0 * ln + jbase;  // element (row0, jbase)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          const int j = jbase + blk_b(b) * 32 + (lane & 31);
+          v4f v;
+          v4i c;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            c[q] = acc[a][b][4 * g + q];
+            if (epi == kEpiCounts) {
+              v[q] = 0.0f;
+            } else if (epi == 2) {
+              v[q] = mi_value64_call(P.m, ci[q], cjb[b], c[q]);
+            } else {
+              v[q] = mi_value32(P.m, ci[q], cjb[b], c[q], a1[q], a0[q], r1b[b], r0b[b], rfm);
+              if (epi == 1 && v[q] < P.tau) v[q] = mi_value64_call(P.m, ci[q], cjb[b], c[q]);
+            }
+          }
+          // Tile rows (i, j): two 128-byte half rows per store.  In a
+          // diagonal tile only j >= i is stored; the mirror fills j < i.
+          const int64_t tb = tile_el + blk_b(b) * 32;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = i0 + q;
+            if (fast || (i < n && j < n && (!diag || j >= i))) {
+              const uint32_t off = lane_tile + (uint32_t)q * row_bytes;
+              if (P.out) *(float*)((char*)(P.out + tb) + off) = v[q];
+              if (P.n11_out) *(int32_t*)((char*)(P.n11_out + tb) + off) = c[q];
+            }
+          }
+          // Mirror (j, i .. i + 3).
+          if (mirror) {
+            const int64_t mb = (int64_t)(jbase + blk_b(b) * 32) * ln + row0;  // element (column block, row0)
+            if (fast) {
+              if (P.out) *(v4f*)((char*)(P.out + mb) + lane_mir) = v;
+              if (P.n11_out) *(v4i*)((char*)(P.n11_out + mb) + lane_mir) = c;
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q;
+                if (i < n && j < n && (!diag || j > i)) {
+                  if (P.out) *(float*)((char*)(P.out + mb) + lane_mir + 4u * q) = v[q];
+                  if (P.n11_out) *(int32_t*)((char*)(P.n11_out + mb) + lane_mir + 4u * q) = c[q];
+                }
+              }
+            }
+          }
+          if (!fast && P.pairs) {
+            // Sparse output: pairs i < j at or above the threshold, one
+            // atomic per wave and register.
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int i = i0 + q;
+              const bool sel = i < n && j < n && j > i && v[q] >= P.thr;
+              const unsigned long long mask = __ballot(sel);
+              if (mask) {  // uniform
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(P.pairs_count, (unsigned long long)__popcll(mask));
+                base = __shfl(base, leader);
+                if (sel) {
+                  const unsigned long long idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+                  if (idx < (unsigned long long)P.pairs_cap) {
+                    int32_t* e3 = P.pairs + 3 * idx;
+                    e3[0] = i;
+                    e3[1] = j;
+                    e3[2] = __float_as_int(v[q]);
+                  }
+                }
+              }
             }
           }
         }
       }
-    };
-    // Two rows per iteration: their independent LDS reads and log2 chains
-    // overlap (two waves per SIMD hide little latency on their own).
-    int rr = 0;
-#pragma clang loop unroll(disable)
-    for (; rr + 1 < rows; rr += 2) {
-      int c0, c1;
-      float v0, v1;
-      eval(rr, c0, v0);
-      eval(rr + 1, c1, v1);
-      // Both rows' values exist here: keeps the compiler from sinking the
-      // second row's arithmetic past the first row's conditional stores.
-      asm volatile("" : "+v"(v0), "+v"(v1), "+v"(c0), "+v"(c1));
-      emit(rr, c0, v0);
-      emit(rr + 1, c1, v1);
-    }
-    if (rr < rows) {
-      int c0;
-      float v0;
-      eval(rr, c0, v0);
-      emit(rr, c0, v0);
     }
   };
-  static_assert(FM <= 4, "the strip switch covers four accumulator blocks");
-  // A wave whose columns all lie past n (tile padding) has nothing to write.
-  const int nstrips = jbase < n ? FM : 0;
-#pragma clang loop unroll(disable)
-  for (int a = 0; a < nstrips; ++a) {
-    switch (a) {
-      case 0: put_strip(std::integral_constant<int, 0>{}); break;
-      case 1: if constexpr (FM > 1) put_strip(std::integral_constant<int, (FM > 1 ? 1 : 0)>{}); break;
-      case 2: if constexpr (FM > 2) put_strip(std::integral_constant<int, (FM > 2 ? 2 : 0)>{}); break;
-      default: if constexpr (FM > 3) put_strip(std::integral_constant<int, (FM > 3 ? 3 : 0)>{}); break;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int i0 = ibase + blk_a(a) * 32;
-    if (i0 >= n) {  // strip rows all past n: skip (uniform)
-      __builtin_amdgcn_wave_barrier();
-      continue;
-    }
+  // The FP32 and counts-only modes have both paths; the FP64 modes, and
+  // every block of a problem with the sparse output, take the tested one.
+  const bool fast = full && !P.pairs;
+  auto rows_mode = [&](auto A0) {
     switch (P.epi) {
-      case 0: strip_rows(i0, std::integral_constant<int, 0>{}); break;
-      case 1: strip_rows(i0, std::integral_constant<int, 1>{}); break;
-      case 2: strip_rows(i0, std::integral_constant<int, 2>{}); break;
-      default: strip_rows(i0, std::integral_constant<int, kEpiCounts>{}); break;
+      case 0:
+        if (fast) emit_rows(A0, std::integral_constant<int, 0>{}, std::true_type{});
+        else emit_rows(A0, std::integral_constant<int, 0>{}, std::false_type{});
+        break;
+      case 1: emit_rows(A0, std::integral_constant<int, 1>{}, std::false_type{}); break;
+      case 2: emit_rows(A0, std::integral_constant<int, 2>{}, std::false_type{}); break;
+      default:
+        if (fast) emit_rows(A0, std::integral_constant<int, kEpiCounts>{}, std::true_type{});
+        else emit_rows(A0, std::integral_constant<int, kEpiCounts>{}, std::false_type{});
+        break;
     }
-    __builtin_amdgcn_wave_barrier();
-    // Mirror rows (consecutive lanes, consecutive i).
-    for (int e = lane; e < STRIP && (P.out || P.n11_out) && !P.upper_only; e += 64) {
-      const int cc = e / 32, rr = e % 32;
-      const int i = i0 + rr, jm = jbase + cc;
-      if (i < n && jm < n && (!diag || jm > i)) {
-        if (P.out) P.out[jm * ln + i] = sM[rr * WTN + cc];
-        if (P.n11_out) P.n11_out[jm * ln + i] = sN[rr * WTN + cc];
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
+  };
+  static_assert(FM == 2 || FM == 4, "block rows are evaluated two at a time");
+  if constexpr (FM == 4) {
+    // 128 accumulators plus the epilogue's working set exceed the two-wave
+    // register budget: block rows 2 and 3 wait in LDS (the ring is free now;
+    // 16 KB per wave, consecutive lanes on consecutive 16 bytes) while rows
+    // 0 and 1 are evaluated.
+    const int sl = wave >> 1;
+    uint8_t* stash = (sl == 0 ? sm.slot[0] : (sl == 1 ? sm.slot[1] : (sl == 2 ? sm.slot[2] : sm.slot[3]))) +
+                     (wave & 1) * 16384;
+    static_assert(C::NWAVES <= 8 && C::STAGE >= 2 * 16384, "two 16 KB stashes per ring slot");
+#pragma unroll
+    for (int a = 2; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          *(MI_LDS v4i*)(stash + ((((a - 2) * FN + b) * 4 + g) * 64 + lane) * 16) =
+              v4i{acc[a][b][4 * g], acc[a][b][4 * g + 1], acc[a][b][4 * g + 2], acc[a][b][4 * g + 3]};
+    rows_mode(std::integral_constant<int, 0>{});
+    // The stashed values must come back from LDS (no forwarding of the
+    // stored registers, which would keep them live).
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int a = 2; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const v4i t = *(const MI_LDS v4i*)(stash + ((((a - 2) * FN + b) * 4 + g) * 64 + lane) * 16);
+          acc[a][b][4 * g] = t.x;
+          acc[a][b][4 * g + 1] = t.y;
+          acc[a][b][4 * g + 2] = t.z;
+          acc[a][b][4 * g + 3] = t.w;
+        }
+    rows_mode(std::integral_constant<int, 2>{});
+  } else {
+    rows_mode(std::integral_constant<int, 0>{});
   }
 #endif
 }
