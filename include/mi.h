@@ -81,9 +81,10 @@ typedef enum mi_algo {
   MI_ALGO_DENSE = 0,   /* int8 matrix-core Gram over upper-triangular tiles (default)        */
   MI_ALGO_SPARSE = 1,  /* sum over rows of the pairs of ones (work ~ m (n d)^2 at density d);  */
                        /* synchronises the stream once                                        */
-  MI_ALGO_AUTO = 2     /* count the ones and their pairs first (one pass, synchronises) and */
-                       /* take whichever path a cost model from measured rates says is     */
-                       /* faster (at 1M x 4096 the sparse one below ~0.3% density)          */
+  MI_ALGO_AUTO = 2     /* estimate the pairs of ones from a 4,096-row sample (synchronises */
+                       /* once); dense when a cost model from measured rates says so       */
+                       /* clearly, else count every row (synchronises again) and take the  */
+                       /* faster path (at 1M x 4096 the sparse one below ~0.3% density)     */
 } mi_algo;
 
 /* Input layouts (mi_problem.packed). */

@@ -8,7 +8,8 @@
 // m n^2 / 2 for density p (the paper's sparse variant wins at the highest
 // sparsity, Section 4.2 / Fig. 3).  Steps, all on the caller's stream:
 //   1. count pass: ones per row and per column (the column sums c);
-//   2. exclusive scan of the row counts -> row offsets (hipCUB);
+//   2. exclusive scan of the row counts -> row offsets (three small
+//      kernels: chunk sums, a one-block scan of the sums, chunk scans);
 //   3. fill pass: the column indices of every row's ones, ascending;
 //   4. pair pass: one wave per row adds 1 to n11[a][b] for every a < b of
 //      its ones (int32 atomics, exact);
@@ -17,9 +18,11 @@
 //      values), tile and mirror written coalesced, optional counts, column
 //      sums and sparse pair list.
 // The total number of ones is read back once (to size the index list), so
-// the call synchronises its stream once.
+// the call synchronises its stream once.  The automatic choice first counts
+// the ones of a sample of rows (one short kernel and a 16-byte read-back);
+// only when the sample leaves the choice open does it run the full count
+// before deciding.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
@@ -33,6 +36,7 @@ namespace mi {
 namespace {
 
 constexpr int kHistCols = 16384;  // column sums in LDS up to this many columns
+constexpr int64_t kSampleRows = 4096;  // rows sampled by the automatic choice
 
 // Ones in the 16-byte chunk [c, c + 16) of a row (bytes past n count 0): the
 // bytes are 0/1, so a dword's ones are its popcount.
@@ -250,6 +254,127 @@ __global__ __launch_bounds__(256) void k_sp_epi(SpEpi E) {
   sp_tile<EPI>(E, I, J);
 }
 
+// 2. Exclusive scan of `count` int64 values, in chunks of kScanChunk per
+//    256-thread block (16 consecutive values per thread).
+constexpr int kScanChunk = 4096;
+
+// Exclusive prefix of v over the block's NT threads; *total receives the sum.
+template <int NT>
+__device__ __forceinline__ int64_t block_exclusive(int64_t v, int64_t* total) {
+  __shared__ int64_t wsum[NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) {
+    before += k < w ? wsum[k] : 0;
+    all += wsum[k];
+  }
+  __syncthreads();  // wsum is reused by the next call
+  *total = all;
+  return before + incl - v;
+}
+
+// Sum of each chunk.
+__global__ __launch_bounds__(256) void k_scan_sums(const int64_t* __restrict__ in, int64_t count,
+                                                   int64_t* __restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + 16 * (int64_t)threadIdx.x;
+  int64_t v = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (base + k < count) v += in[base + k];
+  int64_t total = 0;
+  (void)block_exclusive<256>(v, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the nb chunk sums in place, by one block, 1024 at a time.
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ sums, int64_t nb) {
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += 1024) {  // uniform
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nb ? sums[i] : 0;
+    int64_t total = 0;
+    const int64_t ex = block_exclusive<1024>(v, &total);
+    if (i < nb) sums[i] = carry + ex;
+    carry += total;
+  }
+}
+
+// Each chunk's exclusive scan, offset by the scanned chunk sums.
+__global__ __launch_bounds__(256) void k_scan_apply(const int64_t* __restrict__ in, int64_t count,
+                                                    const int64_t* __restrict__ offs, int64_t* __restrict__ out) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + 16 * (int64_t)threadIdx.x;
+  int64_t v[16];
+  int64_t local = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k] = base + k < count ? in[base + k] : 0;
+    local += v[k];
+  }
+  int64_t total = 0;
+  int64_t run = offs[blockIdx.x] + block_exclusive<256>(local, &total);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (base + k < count) out[base + k] = run;
+    run += v[k];
+  }
+}
+
+// Ones and pairs of ones (k (k - 1) / 2) summed over a sample of rows: row
+// s = 0 .. S - 1 is r = (hash of s + seed) scaled to [0, m).  Each wave takes
+// every (4 gridDim)-th sample, the block adds its waves' sums, and one lane
+// per block adds them to out[0] (ones) and out[1] (pairs).
+__device__ __forceinline__ uint32_t sample_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_sp_sample(const uint8_t* __restrict__ X, int64_t m, int32_t n, int64_t ldx,
+                                                   bool vec, int32_t samples, uint32_t seed,
+                                                   unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[2];
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) part[0] = part[1] = 0ull;
+  __syncthreads();
+  unsigned long long ones = 0, pairs = 0;
+  for (int s = blockIdx.x * 4 + (threadIdx.x >> 6); s < samples; s += gridDim.x * 4) {  // uniform per wave
+    const int64_t r = (int64_t)(((uint64_t)sample_hash((uint32_t)s + seed) * (uint64_t)m) >> 32);
+    const uint8_t* row = X + r * ldx;
+    int cnt = 0;
+    for (int64_t c = 16 * (int64_t)lane; c < n; c += 16 * 64) {
+      uint8_t b[16];
+      chunk_bytes(row, c, n, vec, b);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) cnt += b[k] ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    ones += (unsigned long long)cnt;
+    pairs += (unsigned long long)cnt * (unsigned long long)(cnt > 0 ? cnt - 1 : 0) / 2ull;
+  }
+  if (lane == 0) {
+    atomicAdd(&part[0], ones);
+    atomicAdd(&part[1], pairs);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[0], part[0]);
+    atomicAdd(&out[1], part[1]);
+  }
+}
+
 __global__ void k_fill_i32_64(int32_t* p, int32_t v, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -260,8 +385,9 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-// Density of X (fraction of ones) from the count pass; used by the automatic
-// choice between the dense and the sparse path.  Synchronises the stream.
+// The sparse path, or (auto_choice) the choice between it and the dense path
+// from a row sample, then if needed from the full count.  Synchronises the
+// stream once or twice.
 mi_status run_sparse(const mi_problem* p, int64_t ldx, hipStream_t st, bool auto_choice, bool* used) {
   *used = false;
   const int64_t m = p->m;
@@ -271,17 +397,15 @@ mi_status run_sparse(const mi_problem* p, int64_t ldx, hipStream_t st, bool auto
   mi_status s = device_info(&di);
   if (s != MI_OK) return s;
   // Scratch: row counts/offsets (m + 1 int64), column sums (n int32), the
-  // scan's temporary storage, then (after the count is known) the index list
-  // and the n x n count accumulator.
-  size_t scan_bytes = 0;
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const int64_t*)nullptr, (int64_t*)nullptr,
-                                          (int)std::min<int64_t>(m + 1, INT32_MAX), st));
-  if (m + 1 > INT32_MAX) return fail(MI_ERR_INVALID_ARG, "sparse path: m must be < 2^31 - 1");
+  // scan's chunk sums, the sample's two counters, then (after the count is
+  // known) the index list and the n x n count accumulator.
+  const int64_t scan_blocks = cdiv64(m + 1, kScanChunk);
   const size_t o_nnz = 0;
   const size_t o_ptr = align256(o_nnz + (size_t)(m + 2) * sizeof(int64_t));
   const size_t o_col = align256(o_ptr + (size_t)(m + 1) * sizeof(int64_t));
   const size_t o_scan = align256(o_col + (size_t)n * sizeof(int32_t));
-  const size_t head_bytes = align256(o_scan + scan_bytes);
+  const size_t o_smp = align256(o_scan + (size_t)scan_blocks * sizeof(int64_t));
+  const size_t head_bytes = align256(o_smp + 2 * sizeof(unsigned long long));
   void* head = nullptr;
   s = scratch(st, 2, 0, head_bytes, &head);
   if (s != MI_OK) return s;
@@ -289,32 +413,50 @@ mi_status run_sparse(const mi_problem* p, int64_t ldx, hipStream_t st, bool auto
   int64_t* row_nnz = (int64_t*)(h8 + o_nnz);
   int64_t* row_ptr = (int64_t*)(h8 + o_ptr);
   int32_t* colsum = (int32_t*)(h8 + o_col);
+  int64_t* chunk_sums = (int64_t*)(h8 + o_scan);
   const int blocks = (int)std::min<int64_t>(cdiv64(m, 4), (int64_t)di.cus * 16);
+  // Modelled times (rates measured on this device at 1,000,000 x 4,096):
+  // the dense kernel sustains ~1.4e15 pair-updates/s with the int8 Gram and
+  // ~2.56e15 with the FP4 Gram, after a conversion pass that moves 1.5 bytes
+  // per entry at ~5.1 TB/s; the sparse path reads X twice at ~2.7 TB/s, adds
+  // ~2.8e10 pair counts/s (random int32 atomics) and writes the n^2 output.
+  const double pu = (double)m * (double)n * ((double)n + 1.0) / 2.0;
+  const double dense_s = converts_to_fp4(p) ? pu / 2.56e15 + 1.5 * (double)m * (double)n / 5.1e12 : pu / 1.4e15;
+  auto sparse_s = [&](double pairs) {
+    return (double)m * (double)ldx / 2.7e12 + pairs / 2.8e10 + 4.0 * (double)n * (double)n / 4.0e12;
+  };
+  if (auto_choice && m > 2 * kSampleRows) {
+    // A sample of rows first: its pairs of ones, scaled to m, estimate the
+    // sparse path's work.  Clearly dense (sparse estimated 1.5x slower):
+    // done, without the count pass.
+    unsigned long long* smp = (unsigned long long*)(h8 + o_smp);
+    hipLaunchKernelGGL(k_fill_i32_64, dim3(1), dim3(64), 0, st, (int32_t*)smp, 0, (int64_t)4);
+    hipLaunchKernelGGL(k_sp_sample, dim3((unsigned)std::min<int64_t>(di.cus, cdiv64(kSampleRows, 4))), dim3(256), 0, st, p->X, m, n, ldx, vec,
+                       (int32_t)kSampleRows, 0x9E3779B9u, smp);
+    HIPCHK(hipGetLastError());
+    unsigned long long hs[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(hs, smp, sizeof hs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double est_pairs = (double)hs[1] * (double)m / (double)kSampleRows;
+    if (sparse_s(est_pairs) > 1.5 * dense_s) return MI_OK;  // dense: *used stays false
+  }
   hipLaunchKernelGGL(k_fill_i32_64, dim3(64), dim3(256), 0, st, colsum, 0, (int64_t)n);
   // row_nnz[m] = 0 closes the scan; row_nnz[m + 1] counts the pairs.
   hipLaunchKernelGGL(k_fill_i32_64, dim3(1), dim3(64), 0, st, (int32_t*)(row_nnz + m), 0, (int64_t)4);
   unsigned long long* pair_total = reinterpret_cast<unsigned long long*>(row_nnz + m + 1);
   hipLaunchKernelGGL(k_sp_count, dim3(blocks), dim3(256), 0, st, p->X, m, n, ldx, vec, row_nnz, colsum, pair_total);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(h8 + o_scan, scan_bytes, row_nnz, row_ptr, (int)(m + 1), st));
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)scan_blocks), dim3(256), 0, st, row_nnz, m + 1, chunk_sums);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, chunk_sums, scan_blocks);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)scan_blocks), dim3(256), 0, st, row_nnz, m + 1, chunk_sums, row_ptr);
+  HIPCHK(hipGetLastError());
   int64_t nnz = 0;
   unsigned long long npairs = 0;
   HIPCHK(hipMemcpyAsync(&nnz, row_ptr + m, sizeof nnz, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(&npairs, pair_total, sizeof npairs, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (auto_choice) {
-    // Modelled times (rates measured on this device at 1,000,000 x 4,096):
-    // the dense kernel sustains ~1.4e15 pair-updates/s with the int8 Gram and
-    // ~2.56e15 with the FP4 Gram, after a conversion pass that moves 1.5 bytes
-    // per entry at ~5.1 TB/s; the sparse path reads X twice at ~2.7 TB/s,
-    // adds ~2.8e10 pair counts/s (random int32 atomics) and writes the n^2
-    // output.  The count pass already ran.
-    const double pu = (double)m * (double)n * ((double)n + 1.0) / 2.0;
-    const double dense_s = converts_to_fp4(p) ? pu / 2.56e15 + 1.5 * (double)m * (double)n / 5.1e12 : pu / 1.4e15;
-    const double sparse_s = (double)m * (double)ldx / 2.7e12 + (double)npairs / 2.8e10 +
-                            4.0 * (double)n * (double)n / 4.0e12;
-    if (sparse_s >= dense_s) return MI_OK;  // dense is cheaper: *used stays false
-  }
+  // The exact decision once the count pass ran.
+  if (auto_choice && sparse_s((double)npairs) >= dense_s) return MI_OK;  // dense: *used stays false
   *used = true;
   const size_t cols_bytes = align256((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
   const size_t acc_bytes = align256((size_t)n * (size_t)n * sizeof(int32_t));

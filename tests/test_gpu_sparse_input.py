@@ -87,6 +87,28 @@ def test_auto_and_pairs_output():
     assert lists[0] == lists[1] and len(lists[0]) > 0
 
 
+def test_auto_from_a_row_sample():
+    """More rows than twice the 4,096-row sample: the choice starts from the
+    sample (dense when it is clearly cheaper, else the full count decides)."""
+    say("[sparse-in] auto from a row sample")
+    for density in (0.0005, 0.01, 0.3):
+        X = _sparse_X(23, 40000, 300, density)
+        d = _run(X, 300, mi.MI_ALGO_DENSE)
+        a = _run(X, 300, mi.MI_ALGO_AUTO)
+        assert all(torch.equal(x, y) for x, y in zip(d, a)), density
+
+
+def test_row_offset_scan_over_many_chunks():
+    """4,300,000 rows: the row-offset scan runs more than 1,024 chunks of
+    4,096 rows, so its one-block scan of the chunk sums takes several passes."""
+    say("[sparse-in] 4,300,000 x 40: multi-pass scan")
+    X = _sparse_X(24, 4_300_000, 40, 0.05)
+    d = _run(X, 40, mi.MI_ALGO_DENSE)
+    s = _run(X, 40, mi.MI_ALGO_SPARSE)
+    for a, b, name in zip(d, s, ("MI", "n11", "column sums")):
+        assert torch.equal(a, b), f"sparse-input {name} differ from the dense path"
+
+
 def test_batches_and_server_reject_sparse_algo():
     X = _sparse_X(23, 100, 64, 0.05)
     out = torch.empty((64, 64), device=DEV)
