@@ -101,9 +101,11 @@ typedef enum mi_input {
  * then covers at most 2^24 rows, so every partial count is exact. */
 typedef enum mi_gram {
   MI_GRAM_AUTO = 0,  /* the library's choice: FP4 for byte input with n >= 1536 and       */
-                     /* m n^2 >= 6e10 (converted to the FP4 layout first, in scratch     */
-                     /* memory of half the input's size), for bit input with n >= 512    */
-                     /* (unpacked on chip to FP4 codes), for FP4 input; int8 otherwise   */
+                     /* m n^2 >= 6e10, and for byte input whose layout needs a copy      */
+                     /* (X not 16-byte aligned or ldx % 16 != 0: the conversion replaces */
+                     /* the repack), converted to the FP4 layout first in scratch memory */
+                     /* of half the input's size; for bit input with n >= 512 (unpacked  */
+                     /* on chip to FP4 codes); for FP4 input; int8 otherwise             */
   MI_GRAM_INT8 = 1,  /* v_mfma_i32_32x32x32_i8 on bytes (or bits unpacked to bytes)       */
   MI_GRAM_FP4 = 2    /* v_mfma_scale_f32_32x32x64_f8f6f4 on E2M1 codes: twice the samples */
                      /* per byte staged and ~1.7x the int8 instruction rate               */
@@ -306,7 +308,8 @@ mi_status mi_plan(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* spl
 
 /* Autotuner: time the candidate (tile, splits) configurations for this shape
  * on the current device, with the Gram the library would run for byte input
- * of this shape (FP4 from n >= 1536 and m n^2 >= 6e10, else int8), on a
+ * of this shape and pitch (FP4 from n >= 1536 and m n^2 >= 6e10 or when ldx %
+ * 16 != 0, else int8), on a
  * scratch matrix in that layout holding a hashed 0/1 pattern of density 1/8,
  * and remember the fastest for every later call with the same shape class
  * and Gram.  Each candidate's time is the median of five launches after a

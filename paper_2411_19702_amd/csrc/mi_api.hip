@@ -285,9 +285,17 @@ mi_status choose_plan(int64_t m, int64_t n, bool aligned, int tile_req, int spli
 // the two tie (100,000 x 1,024).
 bool fp4_preferred(int64_t m, int64_t n) { return n >= 1536 && (double)m * (double)n * (double)n >= 6.0e10; }
 
-// Byte input converted to the FP4 layout first (requested, or the library's choice).
+// Byte input converted to the FP4 layout first (requested, or the library's
+// choice).  A layout that the DMA path cannot read (X not 16-byte aligned or
+// ldx % 16 != 0) needs a copy anyway: the conversion writes half the bytes of
+// a repack and the FP4 Gram that follows is the faster one, so the library
+// converts such layouts at every shape.
 bool converts_to_fp4(const mi_problem* p) {
-  return p->packed == MI_INPUT_BYTES && (p->gram == MI_GRAM_FP4 || (p->gram == MI_GRAM_AUTO && fp4_preferred(p->m, p->n)));
+  if (p->packed != MI_INPUT_BYTES) return false;
+  if (p->gram == MI_GRAM_FP4) return true;
+  if (p->gram != MI_GRAM_AUTO) return false;
+  const int64_t ldx = p->ldx == 0 ? p->n : p->ldx;
+  return fp4_preferred(p->m, p->n) || !is_aligned(p->X, ldx);
 }
 
 // Bit-packed input unpacked on chip to FP4 codes: requested, or the
@@ -886,13 +894,14 @@ mi_status tune(int64_t m, int64_t n, int64_t ldx, int32_t* tile, int32_t* splits
   DeviceInfo di;
   mi_status s = device_info(&di);
   if (s != MI_OK) return s;
-  // The Gram the library would run for byte input of this shape.  Unaligned
-  // layouts are repacked (int8) or converted (FP4) to a 16-byte pitch first,
-  // so time on a matrix of that pitch.  It holds a hashed 0/1 pattern of
+  // The Gram the library would run for byte input of this shape and pitch
+  // (FP4 for large shapes and for pitches that are not a multiple of 16,
+  // whose input is converted first), timed on a matrix in the layout that
+  // Gram reads.  It holds a hashed 0/1 pattern of
   // density 1/8 (the kernels' time depends on the data only through the
   // split-K partials they skip when zero, which are then rare).
-  const bool fp4 = fp4_preferred(m, n);
   const bool aligned = ldx % 16 == 0;
+  const bool fp4 = fp4_preferred(m, n) || !aligned;  // unaligned byte layouts are converted to FP4
   const int64_t ld = fp4 ? packed_pitch((n + 1) / 2) : (aligned ? ldx : packed_pitch(n));
   uint8_t* X = nullptr;
   float* out = nullptr;

@@ -102,98 +102,132 @@ __device__ __forceinline__ uint32_t fp4_of(uint32_t d) {
   return ((nz >> 6) & 0x2u) | ((nz >> 10) & 0x20u) | ((nz >> 14) & 0x200u) | ((nz >> 18) & 0x2000u);
 }
 
+// Unaligned sources are read as the aligned 16-byte blocks that hold them.
+// A block is read only when it holds a byte of X ([xbeg, xend) = first to one
+// past the last byte of X): such a block lies in a page that X occupies, so
+// no read can fault; its bytes outside X are never used.  Blocks wholly
+// outside X give zeros.
+__device__ __forceinline__ uint4 load_block(const uint8_t* blk, const uint8_t* xbeg, const uint8_t* xend) {
+  if (blk < xend && blk + 16 > xbeg) return *reinterpret_cast<const uint4*>(blk);
+  return make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Dwords w[0 .. NW - 1] = bytes [src, src + 4 NW) from the NW / 4 + 1 aligned
+// blocks that hold them, shifted into place with v_alignbyte.  The dword
+// offset q = (src mod 16) / 4 selects registers with constant indices.
+template <int NW>
+__device__ __forceinline__ void load_unaligned(const uint8_t* src, const uint8_t* xbeg, const uint8_t* xend,
+                                               uint32_t (&w)[NW]) {
+  constexpr int NB = NW / 4 + 1;
+  const uint8_t* a = reinterpret_cast<const uint8_t*>(reinterpret_cast<uintptr_t>(src) & ~(uintptr_t)15);
+  uint32_t b[4 * NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const uint4 v = load_block(a + 16 * k, xbeg, xend);
+    b[4 * k] = v.x;
+    b[4 * k + 1] = v.y;
+    b[4 * k + 2] = v.z;
+    b[4 * k + 3] = v.w;
+  }
+  const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(src) & 3);
+  const uint32_t q = (uint32_t)(reinterpret_cast<uintptr_t>(src) >> 2) & 3u;
+  if (q == 0) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = __builtin_amdgcn_alignbyte(b[k + 1], b[k], sh);
+  } else if (q == 1) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = __builtin_amdgcn_alignbyte(b[k + 2], b[k + 1], sh);
+  } else if (q == 2) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = __builtin_amdgcn_alignbyte(b[k + 3], b[k + 2], sh);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = __builtin_amdgcn_alignbyte(b[k + 4], b[k + 3], sh);
+  }
+}
+
+// Bytes at or past `avail` (of the 4 NW) set to 0.
+template <int NW>
+__device__ __forceinline__ void zero_past(int64_t avail, uint32_t (&w)[NW]) {
+  if (avail >= 4 * NW) return;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int64_t keep = avail - 4 * k;  // bytes of dword k to keep
+    w[k] = keep >= 4 ? w[k] : (keep <= 0 ? 0u : (w[k] & ((1u << (8 * keep)) - 1u)));
+  }
+}
+
 // FP4 codes of 32 columns from src (avail = columns of the row from src on;
-// those past it are 0), as 16 bytes.  A 16-byte-aligned source inside the
-// row is two 16-byte loads; otherwise, when the nine aligned dwords around it
-// lie inside X ([xbeg, xend) = first to one past the last byte read), they
-// are loaded and shifted into place with v_alignbyte (as the repack does);
-// anything else goes byte by byte.
+// those past it are 0), as 16 bytes.  A 16-byte-aligned source is two
+// 16-byte loads; any other goes through the aligned blocks around it.
 __device__ __forceinline__ uint4 fp4_pack32(const uint8_t* src, int64_t avail, const uint8_t* xbeg,
                                             const uint8_t* xend) {
   uint32_t w[8];
-  const uint8_t* lo = reinterpret_cast<const uint8_t*>(reinterpret_cast<uintptr_t>(src) & ~(uintptr_t)3);
   if (avail >= 32 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
     const uint4 a = *reinterpret_cast<const uint4*>(src);
     const uint4 b = *reinterpret_cast<const uint4*>(src + 16);
     w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
     w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
-  } else if (avail >= 32 && lo >= xbeg && lo + 36 <= xend) {
-    const uint32_t* p = reinterpret_cast<const uint32_t*>(lo);
-    uint32_t a[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = p[k];
-    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(src) & 3);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) w[k] = __builtin_amdgcn_alignbyte(a[k + 1], a[k], sh);
   } else {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      uint32_t v = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (4 * k + b < avail) v |= (uint32_t)src[4 * k + b] << (8 * b);
-      w[k] = v;
-    }
+    load_unaligned<8>(src, xbeg, xend, w);
+    zero_past<8>(avail, w);
   }
   return make_uint4(fp4_of(w[0]) | (fp4_of(w[1]) << 16), fp4_of(w[2]) | (fp4_of(w[3]) << 16),
                     fp4_of(w[4]) | (fp4_of(w[5]) << 16), fp4_of(w[6]) | (fp4_of(w[7]) << 16));
 }
 
-// One 16-byte chunk of an FP4 conversion: columns [32 c, 32 c + 32) of one
-// row, zeros past n.
-__device__ __forceinline__ void fp4_chunk(const RepackDesc& d, int64_t q) {
-  const int64_t segs = d.ldy >> 4;
-  const int64_t row = q / segs;
-  const int64_t c = q - row * segs;
-  const uint8_t* xend = d.X + (d.m - 1) * d.ldx + d.n;
-  const uint4 o = fp4_pack32(d.X + row * d.ldx + 32 * c, d.n - 32 * c, d.X, xend);
-  *reinterpret_cast<uint4*>(d.Y + row * d.ldy + 16 * c) = o;
-}
-
-// Y[r][c] = X[r][c] for c < n, 0 for n <= c < ldy: a 16-byte aligned copy with
-// pitch ldy (a multiple of 16) for layouts the DMA path cannot read directly.
-// Repack of a layout the DMA path cannot read (base or pitch not a multiple of
-// 16 bytes) into a 16-byte pitch.  One thread writes one 16-byte chunk of Y:
-// columns [c, c + 16) of one row, zeros past n.  Inside X it reads the five
-// aligned dwords around the chunk and shifts them into place; chunks whose
-// window would reach outside [X, last valid byte] read byte by byte.
-__device__ __forceinline__ void repack_chunk(const RepackDesc& d, int64_t q) {
-  const int64_t segs = d.ldy >> 4;
-  const int64_t row = q / segs;
-  const int64_t c = (q - row * segs) * 16;
-  const uint8_t* src = d.X + row * d.ldx + c;
-  const uint8_t* lo = reinterpret_cast<const uint8_t*>(reinterpret_cast<uintptr_t>(src) & ~(uintptr_t)3);
-  const uint8_t* end = d.X + (d.m - 1) * d.ldx + d.n;  // one past the last byte of X that is read
-  uint32_t w[4];
-  if (c + 16 <= d.n && lo >= d.X && lo + 20 <= end) {
-    const uint32_t* p = reinterpret_cast<const uint32_t*>(lo);
-    const uint32_t a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3], a4 = p[4];
-    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(src) & 3);
-    w[0] = __builtin_amdgcn_alignbyte(a1, a0, sh);
-    w[1] = __builtin_amdgcn_alignbyte(a2, a1, sh);
-    w[2] = __builtin_amdgcn_alignbyte(a3, a2, sh);
-    w[3] = __builtin_amdgcn_alignbyte(a4, a3, sh);
+// Chunk c of row r of a repack or conversion (d.fp4): Y's row r gets at
+// 16 c the bytes [16 c, 16 c + 16) of X's row (a repack) or the FP4 codes of
+// its columns [32 c, 32 c + 32) (a conversion); zeros past n.
+__device__ __forceinline__ void stage_chunk(const RepackDesc& d, int64_t r, int64_t c) {
+  const uint8_t* xend = d.X + (d.m - 1) * d.ldx + d.n;  // one past the last byte of X that is read
+  const uint8_t* row = d.X + r * d.ldx;
+  uint4 o;
+  if (d.fp4) {
+    o = fp4_pack32(row + 32 * c, d.n - 32 * c, d.X, xend);
   } else {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      uint32_t v = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (c + 4 * k + b < d.n) v |= (uint32_t)src[4 * k + b] << (8 * b);
-      w[k] = v;
-    }
+    uint32_t w[4];
+    load_unaligned<4>(row + 16 * c, d.X, xend, w);
+    zero_past<4>(d.n - 16 * c, w);
+    o = make_uint4(w[0], w[1], w[2], w[3]);
   }
-  *reinterpret_cast<uint4*>(d.Y + row * d.ldy + c) = uint4{w[0], w[1], w[2], w[3]};
+  *reinterpret_cast<uint4*>(d.Y + r * d.ldy + 16 * c) = o;
 }
 
+// Rows per wave of a layout: one wave per row when a row has 64 or more
+// 16-byte chunks, else 64 / chunks rows side by side (so narrow rows keep
+// the lanes busy).
+__host__ __device__ inline int64_t rows_per_wave(int64_t ldy) {
+  const int64_t cpr = ldy >> 4;
+  return cpr >= 64 ? 1 : 64 / (cpr > 0 ? cpr : 1);
+}
+
+// Wave w0, w0 + wstride, ... of a layout: its group of rows_per_wave rows,
+// consecutive lanes on consecutive chunks.
+__device__ __forceinline__ void stage_rows(const RepackDesc& d, int64_t w0, int64_t wstride, int lane) {
+  const int64_t cpr = d.ldy >> 4;
+  if (cpr >= 64) {
+    for (int64_t r = w0; r < d.m; r += wstride)
+      for (int64_t c = lane; c < cpr; c += 64) stage_chunk(d, r, c);
+    return;
+  }
+  const int rpw = (int)rows_per_wave(d.ldy);
+  const int lr = lane / (int)cpr, c = lane - lr * (int)cpr;
+  for (int64_t g = w0; g * rpw < d.m; g += wstride) {
+    const int64_t r = g * rpw + lr;
+    if (lr < rpw && r < d.m) stage_chunk(d, r, c);
+  }
+}
+
+// Repack of a layout the DMA path cannot read (base or pitch not a multiple
+// of 16 bytes) into a 16-byte pitch: 4 waves per block, the grid strides
+// over the row groups.
 __global__ __launch_bounds__(256) void k_repack(RepackDesc d) {
-  const int64_t total = d.m * (d.ldy >> 4);
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256)
-    repack_chunk(d, q);
+  stage_rows(d, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), (int64_t)gridDim.x * 4, threadIdx.x & 63);
 }
 
-// All repacks of a batch in one launch: block b belongs to the dataset whose
-// block range [first_block, first_block + blocks) holds it.
+// All repacks and conversions of a batch in one launch: block b belongs to
+// the dataset whose block range [first_block, first_block + blocks) holds it.
 __global__ __launch_bounds__(256) void k_repack_batch(const RepackDesc* __restrict__ descs, int count) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = count - 1;
@@ -203,12 +237,7 @@ __global__ __launch_bounds__(256) void k_repack_batch(const RepackDesc* __restri
     else hi = mid - 1;
   }
   const RepackDesc d = descs[lo];
-  const int64_t total = d.m * (d.ldy >> 4);
-  if (d.fp4) {  // uniform
-    for (int64_t q = (b - d.first_block) * 256 + threadIdx.x; q < total; q += d.blocks * 256) fp4_chunk(d, q);
-  } else {
-    for (int64_t q = (b - d.first_block) * 256 + threadIdx.x; q < total; q += d.blocks * 256) repack_chunk(d, q);
-  }
+  stage_rows(d, (b - d.first_block) * 4 + (threadIdx.x >> 6), d.blocks * 4, threadIdx.x & 63);
 }
 
 // Byte -> bit packing (the layout of a packed problem).  0x01 in each
@@ -375,10 +404,11 @@ hipError_t launch_validate_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t l
   return hipGetLastError();
 }
 
-// Blocks for one layout: one 16-byte chunk per thread, at most 65536 blocks
-// (larger layouts loop).
+// Blocks for one layout: four waves per block, one group of rows per wave
+// (rows_per_wave), at most 65536 blocks (more groups loop).
 int64_t repack_blocks(int64_t m, int64_t ldy) {
-  const int64_t b = (m * (ldy >> 4) + 255) / 256;
+  const int64_t rpw = rows_per_wave(ldy);
+  const int64_t b = ((m + rpw - 1) / rpw + 3) / 4;
   return b < 65536 ? (b > 0 ? b : 1) : 65536;
 }
 

@@ -222,7 +222,8 @@ def test_fp4_gram_on_bytes_in_batches(mode, tile):
 
 def test_fp4_validate_and_plan_ex():
     """validate checks the bytes before the FP4 conversion; mi_plan_ex reports
-    the Gram each call runs (FP4 from n >= 1536 and m n^2 >= 6e10)."""
+    the Gram each call runs (FP4 from n >= 1536 and m n^2 >= 6e10, and for
+    layouts that need a copy)."""
     X = (torch.rand((3000, 1600), device=DEV) < 0.3).to(torch.uint8)
     out = mi.mi_all_pairs_ex(X, validate=True, gram=mi.MI_GRAM_FP4)
     want = mi.mi_all_pairs_ex(X, gram=mi.MI_GRAM_INT8)
@@ -237,6 +238,8 @@ def test_fp4_validate_and_plan_ex():
     assert mi.mi_plan_ex(big[:5000])[2] == mi.MI_GRAM_INT8  # 2.1e10
     assert mi.mi_plan_ex(big[:, :1024])[2] == mi.MI_GRAM_INT8
     assert mi.mi_plan_ex(big, gram=mi.MI_GRAM_INT8)[2] == mi.MI_GRAM_INT8
+    assert mi.mi_plan_ex(big[:5000, 1:1001])[2] == mi.MI_GRAM_FP4   # unaligned: converted, not repacked
+    assert mi.mi_plan_ex(big[:5000, :1000])[2] == mi.MI_GRAM_INT8   # pitch 2048, aligned
     assert mi.mi_plan_ex(big[:5000], gram=mi.MI_GRAM_FP4)[2] == mi.MI_GRAM_FP4
     Q = mi.mi_pack_fp4(big[:100])
     assert mi.mi_plan_ex(Q, n=2048, packed=mi.MI_INPUT_FP4)[2] == mi.MI_GRAM_FP4

@@ -276,3 +276,29 @@ def test_counts_only_call():
     torch.cuda.synchronize()
     assert r is None
     assert np.array_equal(n11_c.cpu().numpy(), n11) and np.array_equal(cs_c.cpu().numpy(), cs)
+
+
+@pytest.mark.parametrize("offset", list(range(16)))
+def test_every_base_offset_and_ragged_width(offset):
+    """Unaligned layouts are repacked (int8 Gram) or converted (FP4 Gram) from
+    the aligned 16-byte blocks around each row: every base offset 0..15 with
+    widths around block edges gives the aligned copy's outputs bitwise, and
+    the conversion call matches a plain nibble packing."""
+    rng = np.random.default_rng(700 + offset)
+    for m, n, pitch in ((37, 1, 19), (64, 15, 31), (33, 16, 16), (50, 17, 40), (21, 33, 59), (40, 100, 117)):
+        say(f"[offset] {offset} m={m} n={n} pitch={pitch}")
+        buf = torch.from_numpy((rng.random((m * pitch + offset + 64,)) < 0.3).astype(np.uint8)).to(DEV)
+        X = buf[offset:offset + m * pitch].view(m, pitch)[:, :n]
+        ref = X.contiguous()
+        for gram in (mi.MI_GRAM_INT8, mi.MI_GRAM_FP4):
+            a = run_gpu(X, gram=gram)
+            b = run_gpu(ref, gram=gram)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (offset, m, n, pitch, gram)
+        compare_full(ref.cpu().numpy(), n, *run_gpu(X, gram=mi.MI_GRAM_FP4))
+        Q = mi.mi_pack_fp4(X, n)
+        torch.cuda.synchronize()
+        nz = (ref.cpu().numpy() != 0).astype(np.uint8) * 2
+        if n % 2:
+            nz = np.concatenate([nz, np.zeros((m, 1), np.uint8)], axis=1)
+        assert np.array_equal(Q.cpu().numpy()[:, :(n + 1) // 2], (nz[:, 0::2] | (nz[:, 1::2] << 4)).astype(np.uint8))

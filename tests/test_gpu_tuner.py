@@ -21,10 +21,13 @@ def _clear_tuner():
     mi.mi_tuner_clear()
 
 
-@pytest.mark.parametrize("m,n,gram", [(20000, 700, mi.MI_GRAM_INT8), (2000, 8192, mi.MI_GRAM_FP4)])
-def test_tuned_plan_is_used_and_results_unchanged(m, n, gram):
-    say(f"[tune] {m}x{n}")
-    X = synth.generate(synth.spec_random(61, m, n, 0.0, 0.6, planted=4), device=DEV)
+@pytest.mark.parametrize("m,n,pitch,gram", [(20000, 700, 704, mi.MI_GRAM_INT8), (20000, 700, 700, mi.MI_GRAM_FP4),
+                                            (2000, 8192, 8192, mi.MI_GRAM_FP4)])
+def test_tuned_plan_is_used_and_results_unchanged(m, n, pitch, gram):
+    """int8 for an aligned pitch; FP4 for a large shape and for a pitch that
+    is not a multiple of 16 (its conversion replaces the repack)."""
+    say(f"[tune] {m}x{n} pitch {pitch}")
+    X = synth.generate(synth.spec_random(61, m, n, 0.0, 0.6, ldx=pitch, planted=4), device=DEV)[:, :n]
     before = mi.mi_all_pairs_ex(X)
     torch.cuda.synchronize()
     assert mi.mi_plan_ex(X)[2] == gram
