@@ -91,7 +91,7 @@ struct ProbDev {
   float* out;
   int32_t* n11_out;     // optional
   int32_t* colsum_out;  // optional
-  int32_t* ws_n11;      // partial units: ntiles * BT * BT int32, all zero between calls
+  int32_t* ws_n11;      // partial units: ntiles * BT * BT int32 (register order), all zero between calls
   int32_t* ws_col;      // partial units: ntiles * 2 * BT int32
   int32_t* counters;    // partial units: ntiles int32 (row steps arrived)
   const int32_t* tiles; // tile order: ntiles entries of (I << 16) | J; nullptr: decoded from the rank
@@ -807,20 +807,28 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
   __syncthreads();
 
   // Partial unit: publish partials; the unit that completes the tile's row
-  // steps takes over.
+  // steps takes over.  The tile's workspace holds the counts in register
+  // order (wave, block, register pair, lane): every unit's wave w holds the
+  // same elements in the same registers, so the order only has to agree
+  // between units.  Registers 2 k and 2 k + 1 go out as one 64-bit atomic
+  // add of the two int32 counts packed side by side: every partial count is
+  // non-negative and their total is at most m < 2^31, so the low half never
+  // carries into the high one and both sums are exact.  One instruction
+  // covers 512 consecutive bytes.
+  static_assert(C::NWAVES * FM * FN * 16 * 64 == BT * BT, "the register order covers the tile's workspace");
   if (!whole) {
-    int32_t* wsn = P.ws_n11 + (int64_t)t * BT * BT;
+    unsigned long long* wsn = reinterpret_cast<unsigned long long*>(P.ws_n11 + (int64_t)t * BT * BT) +
+                              (int64_t)wave * (FM * FN * 8 * 64) + lane;
     int32_t* wsc = P.ws_col + (int64_t)t * 2 * BT;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = wm * C::WTM + blk_a(a) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int col = wn * C::WTN + blk_b(b) * 32 + (lane & 31);
-          const int v = acc[a][b][r];
-          if (v) __hip_atomic_fetch_add(&wsn[row * BT + col], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < 8; ++k) {
+          const unsigned long long v = (unsigned long long)(uint32_t)acc[a][b][2 * k] |
+                                       ((unsigned long long)(uint32_t)acc[a][b][2 * k + 1] << 32);
+          if (v) __hip_atomic_fetch_add(wsn + ((a * FN + b) * 8 + k) * 64, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     for (int c = tid; c < 2 * BT; c += C::NT) {
       const int v = sColA[c];
@@ -843,21 +851,17 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = wm * C::WTM + blk_a(a) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int col = wn * C::WTN + blk_b(b) * 32 + (lane & 31);
-          acc[a][b][r] = wsn[row * BT + col];
+        for (int k = 0; k < 8; ++k) {
+          const unsigned long long v = wsn[((a * FN + b) * 8 + k) * 64];
+          acc[a][b][2 * k] = (int)(uint32_t)v;
+          acc[a][b][2 * k + 1] = (int)(uint32_t)(v >> 32);
         }
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = wm * C::WTM + blk_a(a) * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-          const int col = wn * C::WTN + blk_b(b) * 32 + (lane & 31);
-          wsn[row * BT + col] = 0;
-        }
+        for (int k = 0; k < 8; ++k) wsn[((a * FN + b) * 8 + k) * 64] = 0ull;
     __syncthreads();
     for (int c = tid; c < 2 * BT; c += C::NT) {
       sColA[c] = wsc[c];
