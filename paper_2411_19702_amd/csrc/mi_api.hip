@@ -522,12 +522,14 @@ static std::string batch_key(const mi_problem* probs, int64_t count, const std::
 //   fdiv: each dataset is split so that no unit is much larger than the
 //        batch's MAC work over (persistent slots x fdiv); units of very
 //        different datasets then balance in the dynamic queue.
-// The heuristic is {kBatchTileAuto, 512, 4}; the batch tuner (mi_tune_batched)
+// The heuristic is {kBatchTileAuto, 512, 1} (units at most one slot's share:
+// with splits published by atomics and units sorted by decreasing rows, fewer
+// and larger units measured faster); the batch tuner (mi_tune_batched)
 // times candidates on the caller's batch and stores the fastest under the
 // batch's signature.
 constexpr int kBatchTileAuto = 0, kBatchTileByWidth = 3;
 
-static BatchChoice heuristic_batch_choice() { return BatchChoice{kBatchTileAuto, 512, 4}; }
+static BatchChoice heuristic_batch_choice() { return BatchChoice{kBatchTileAuto, 512, 1}; }
 
 // Batch signature: the multiset of the datasets' shape classes (the single
 // tuner's m and n classes), layouts, Gram choices and explicit tile / split
@@ -1026,7 +1028,7 @@ mi_status tune_batched(const mi_problem* probs, int64_t count, hipStream_t st, d
   for (const auto& tn : tiles)
     for (int fdiv : {1, 2, 4, 8, 16}) {
       const BatchChoice c{tn.first, tn.second, fdiv};
-      if (c.tile == kBatchTileAuto && c.fdiv == 4) continue;  // the heuristic, already first
+      if (c.tile == kBatchTileAuto && c.fdiv == 1) continue;  // the heuristic, already first
       cands.push_back(c);
     }
   hipEvent_t e0 = nullptr, e1 = nullptr;

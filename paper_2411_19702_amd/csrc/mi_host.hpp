@@ -74,7 +74,7 @@ void release_stream_resources(hipStream_t st);  // scratch and batch descriptors
 struct BatchChoice {
   int tile = 0;        // 0: one tile by the work's majority width; MI_TILE_128 / _256; 3: by dataset width
   int narrow_n = 512;  // tile 3: datasets narrower than this take 128-wide tiles
-  int fdiv = 4;        // K-split target: the batch's work over (persistent slots x fdiv)
+  int fdiv = 1;        // K-split target: the batch's work over (persistent slots x fdiv)
 };
 // choice: the persistent mode's plan (nullptr: the tuned one for this batch, else the heuristic).
 // plans_out: planning query (checks and plans only, nothing launched or allocated).
