@@ -554,7 +554,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_1000000x4096", choices=sorted(WORKLOADS))
     ap.add_argument("--epilogue", type=int, default=0, help="0 fp32, 1 fp32 + fp64 fallback, 2 fp64")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time for cpu_baseline (0: skip)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner for this shape first")
     ap.add_argument("--pitch", type=int, default=0, help="row pitch of X in bytes (0: dense, pitch = n)")
     ap.add_argument("--shape", default="", help="M,N: time a random M x N matrix instead of a named workload")

@@ -102,7 +102,10 @@ mi_status scratch(hipStream_t st, int kind, int slot, size_t bytes, void** out) 
       w.ptr = nullptr;
       return fail(MI_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes failed", sz);
     }
-    if (kind == 0) HIPCHK(hipMemset(w.ptr, 0, sz));
+    // Zeroed on the stream that uses it: a memset on the legacy default
+    // stream is not ordered before kernels on a non-blocking stream (the
+    // server's), which could then add into a workspace not yet cleared.
+    if (kind == 0) HIPCHK(fill_zero(w.ptr, sz, st));
     w.bytes = sz;
   }
   *out = w.ptr;

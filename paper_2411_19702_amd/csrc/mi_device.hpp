@@ -346,6 +346,7 @@ struct Smem {
   uint8_t* slot[4];
   int32_t* cols;  // 2 * BT + 4 int32
   float* rcp;     // 4 * BT float
+  float* mir;     // epilogue mirror buffers (NWAVES x 16 x 36 float), or nullptr: in the ring
 };
 
 // Bit-packed input: 16 columns from 2 packed bytes (the low 16 bits of w,
@@ -920,19 +921,27 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
     r0b[b] = rB0[jl];
   }
   // Addresses: a wave-uniform 64-bit base per group of rows plus this lane's
-  // 32-bit byte offset (tile rows: row 4 (lane / 32), column lane % 32;
-  // mirror rows: row lane % 32, column 4 (lane / 32)).  The offsets stay
-  // below 2^32 for n below 2^25.
+  // 32-bit byte offset (tile rows: row 4 (lane / 32), column lane % 32).  The
+  // offsets stay below 2^32 for n below 2^25.
   const uint32_t lane_tile = (uint32_t)(((lane >> 5) * 4) * n + (lane & 31)) * 4u;
   const uint32_t lane_mir = (uint32_t)((lane & 31) * n + (lane >> 5) * 4) * 4u;
   const uint32_t row_bytes = (uint32_t)n * 4u;
-  // Mirror stores of four consecutive rows as one 16-byte store need 16-byte
-  // aligned outputs and n % 4 == 0.
+  // 16-byte mirror stores need 16-byte aligned outputs and n % 4 == 0.
   const bool vec = (n & 3) == 0 && ((uintptr_t)P.out & 15) == 0 && ((uintptr_t)P.n11_out & 15) == 0;
   // A block strictly above the diagonal (every j > i) and inside the matrix
   // stores without per-element tests.
   const bool full = ibase + C::WTM <= n && jbase + C::WTN <= n && jbase >= ibase + C::WTM && vec;
   const bool mirror = !P.upper_only && (P.out || P.n11_out);
+  // The FP32 mirror goes through LDS: a lane's registers 4 g .. 4 g + 3 are
+  // four consecutive mirror columns of one mirror row, but 32 rows per store
+  // would write a quarter of each 128-byte line per instruction (measured:
+  // a third more bytes written than the output).  Half a 32 x 32 block at a
+  // time (16 mirror rows, padded to 36 floats against bank conflicts) is
+  // transposed in a per-wave LDS buffer and stored as whole rows, 8 lanes per
+  // row.  The buffer is in the ring (128-wide tiles) or its own array.
+  constexpr int kMirPitch = 36;
+  float* mbuf = sm.mir ? sm.mir + wave * (16 * kMirPitch)
+                       : reinterpret_cast<float*>(wave == 0 ? sm.slot[0] : (wave == 1 ? sm.slot[1] : (wave == 2 ? sm.slot[2] : sm.slot[3])));
   // Evaluate and store accumulator block rows [A0, A0 + 2).  The epilogue
   // mode and the block test are template arguments, so the FP32 path carries
   // neither mode tests nor bounds tests; the sparse output goes with the
@@ -945,20 +954,22 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
 #pragma unroll
     for (int a = decltype(A0)::value; a < decltype(A0)::value + 2 && a < FM; ++a) {
       if (ibase + blk_a(a) * 32 >= n) continue;  // block rows past n (uniform)
+      const int ia = I * BT + wm * C::WTM + blk_a(a) * 32;  // first row of the block row
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        __builtin_amdgcn_sched_barrier(0);
-        const int il = wm * C::WTM + blk_a(a) * 32 + g * 8;  // tile row of lane 0's register 4 g
-        const int row0 = I * BT + il;
-        const int i0 = row0 + (lane >> 5) * 4;               // this lane's row of register 4 g
-        const int ill = il + (lane >> 5) * 4;
-        const v4f a1 = *(const MI_LDS v4f*)(const MI_LDS float*)(rA1 + ill);
-        const v4f a0 = *(const MI_LDS v4f*)(const MI_LDS float*)(rA0 + ill);
-        const v4i ci = *(const MI_LDS v4i*)(const MI_LDS int32_t*)(sColA + ill);
-        const int64_t tile_el = (int64_t)row0 * ln + jbase;  // element (row0, jbase)
+      for (int b = 0; b < FN; ++b) {
+        const int jb = jbase + blk_b(b) * 32;  // first column of the block
+        const int j = jb + (lane & 31);
+        if (jb >= n) continue;  // uniform
+        v4f vs[4];  // this lane's values of register groups g = 0 .. 3
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          const int j = jbase + blk_b(b) * 32 + (lane & 31);
+        for (int g = 0; g < 4; ++g) {
+          __builtin_amdgcn_sched_barrier(0);
+          const int il = wm * C::WTM + blk_a(a) * 32 + g * 8 + (lane >> 5) * 4;  // tile row of register 4 g
+          const int row0 = ia + g * 8;
+          const int i0 = il + I * BT;
+          const v4f a1 = *(const MI_LDS v4f*)(const MI_LDS float*)(rA1 + il);
+          const v4f a0 = *(const MI_LDS v4f*)(const MI_LDS float*)(rA0 + il);
+          const v4i ci = *(const MI_LDS v4i*)(const MI_LDS int32_t*)(sColA + il);
           v4f v;
           v4i c;
 #pragma unroll
@@ -973,9 +984,10 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
               if (epi == 1 && v[q] < P.tau) v[q] = mi_value64_call(P.m, ci[q], cjb[b], c[q]);
             }
           }
+          vs[g] = v;
           // Tile rows (i, j): two 128-byte half rows per store.  In a
           // diagonal tile only j >= i is stored; the mirror fills j < i.
-          const int64_t tb = tile_el + blk_b(b) * 32;
+          const int64_t tb = (int64_t)row0 * ln + jb;  // element (row0, jb)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int i = i0 + q;
@@ -985,20 +997,16 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
               if (P.n11_out) *(int32_t*)((char*)(P.n11_out + tb) + off) = c[q];
             }
           }
-          // Mirror (j, i .. i + 3).
-          if (mirror) {
-            const int64_t mb = (int64_t)(jbase + blk_b(b) * 32) * ln + row0;  // element (column block, row0)
+          // The counts' mirror (j, i .. i + 3) directly (a rare output).
+          if (mirror && P.n11_out) {
+            const int64_t mb = (int64_t)jb * ln + row0;
             if (fast) {
-              if (P.out) *(v4f*)((char*)(P.out + mb) + lane_mir) = v;
-              if (P.n11_out) *(v4i*)((char*)(P.n11_out + mb) + lane_mir) = c;
+              *(v4i*)((char*)(P.n11_out + mb) + lane_mir) = c;
             } else {
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const int i = i0 + q;
-                if (i < n && j < n && (!diag || j > i)) {
-                  if (P.out) *(float*)((char*)(P.out + mb) + lane_mir + 4u * q) = v[q];
-                  if (P.n11_out) *(int32_t*)((char*)(P.n11_out + mb) + lane_mir + 4u * q) = c[q];
-                }
+                if (i < n && j < n && (!diag || j > i)) *(int32_t*)((char*)(P.n11_out + mb) + lane_mir + 4u * q) = c[q];
               }
             }
           }
@@ -1024,6 +1032,43 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
                     e3[2] = __float_as_int(v[q]);
                   }
                 }
+              }
+            }
+          }
+        }
+        // The FP32 mirror of block (a, b): mirror rows jb .. jb + 31, columns
+        // ia .. ia + 31, in two halves of 16 rows.  Lanes l and l + 32 hold
+        // mirror row jb + l % 32; each writes its four 16-byte groups into
+        // the buffer, then 8 lanes per row read whole rows and store them.
+        // The lanes exchange data through LDS, so the compiler must not move
+        // the reads above the other lanes' writes, nor the next half's writes
+        // above this half's reads: a memory-clobbering wait orders both (LDS
+        // operations of one wave then complete in order).
+        if (mirror && P.out) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            if (((lane & 31) >> 4) == h) {
+#pragma unroll
+              for (int g = 0; g < 4; ++g)
+                *(MI_LDS v4f*)(mbuf + (lane & 15) * kMirPitch + g * 8 + (lane >> 5) * 4) = vs[g];
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const int rr = k * 8 + (lane >> 3);  // buffer row
+              const int jm = jb + h * 16 + rr;     // mirror row
+              const int ic = ia + (lane & 7) * 4;  // first of its four columns
+              const v4f t = *(const MI_LDS v4f*)(mbuf + rr * kMirPitch + (lane & 7) * 4);
+              float* dst = P.out + (int64_t)jm * ln + ic;
+              if (fast) {
+                *(v4f*)dst = t;
+              } else if (vec && jm < n && ic + 3 < n && (!diag || jm > ic + 3)) {
+                *(v4f*)dst = t;
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (jm < n && ic + e < n && (!diag || jm > ic + e)) dst[e] = t[e];
               }
             }
           }

@@ -48,6 +48,7 @@ hipError_t launch_pack_bits(const uint8_t* X, int64_t m, int64_t n, int64_t ldx,
 hipError_t launch_pack_fp4(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, uint8_t* Xq, int64_t ldq,
                            hipStream_t st);
 hipError_t fill_i32(int* p, int v, int count, hipStream_t st);
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);  // bytes a multiple of 4
 hipError_t launch_fill_pattern(uint8_t* X, int64_t m, int64_t ld, int64_t bytes, bool fp4, hipStream_t st);
 int occupancy(int cfg);
 int persistent_occupancy(int cfg, bool fp4);

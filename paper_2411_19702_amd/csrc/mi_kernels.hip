@@ -1,4 +1,6 @@
 // mi_kernels.hip -- kernel entry points and their launchers.
+#include <algorithm>
+
 #include "mi_device.hpp"
 #include "mi_internal.hpp"
 
@@ -11,7 +13,8 @@ namespace mi {
   __shared__ __attribute__((aligned(16))) uint8_t ring3_[C::STAGE];         \
   __shared__ __attribute__((aligned(16))) int32_t cols_[2 * C::BT + 4];     \
   __shared__ __attribute__((aligned(16))) float rcp_[4 * C::BT];            \
-  const Smem<C> sm{{ring0_, ring1_, ring2_, ring3_}, cols_, rcp_}
+  __shared__ __attribute__((aligned(16))) float mir_[C::BT == 256 ? C::NWAVES * 16 * 36 : 4]; \
+  const Smem<C> sm{{ring0_, ring1_, ring2_, ring3_}, cols_, rcp_, C::BT == 256 ? mir_ : nullptr}
 
 // Plain launch of one dataset: one workgroup per (tile, K split) unit.
 // Workgroup u runs on XCD u % 8.  XCD x owns the tile ranks
@@ -426,6 +429,19 @@ hipError_t launch_repack(const uint8_t* X, int64_t m, int64_t n, int64_t ldx, ui
 hipError_t launch_repack_batch(const RepackDesc* descs, int count, int64_t blocks, hipStream_t st) {
   if (count <= 0 || blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_repack_batch, dim3((unsigned)blocks), dim3(256), 0, st, descs, count);
+  return hipGetLastError();
+}
+
+// bytes / 4 int32 zeros at p (bytes a multiple of 4), grid-strided.
+__global__ __launch_bounds__(256) void k_zero_i32(int* __restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const int64_t count = (int64_t)(bytes / 4);
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)blocks), dim3(256), 0, st, (int*)p, count);
   return hipGetLastError();
 }
 
