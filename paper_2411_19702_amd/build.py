@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmi.so")
 
-SOURCES = ["mi_kernels.hip", "mi_sparse.hip", "mi_categorical.hip", "mi_api.hip", "mi_noalloc.hip", "mi_server.cpp"]
+SOURCES = ["mi_kernels.hip", "mi_layout.hip", "mi_sparse.hip", "mi_categorical.hip", "mi_api.hip", "mi_noalloc.hip", "mi_server.cpp"]
 HEADERS = ["mi_device.hpp", "mi_internal.hpp", "mi_host.hpp"]
 
 # -packed-fp32-ops: keep hipcc from emitting packed FP32 instructions.
