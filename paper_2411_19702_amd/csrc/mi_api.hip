@@ -618,6 +618,33 @@ static mi_status plan_persistent(const mi_problem* probs, int64_t count, const s
   return MI_OK;
 }
 
+// The Gram of each dataset of a batch (conv: converted from bytes first; f4:
+// runs the FP4 Gram), by each problem's own choice.  In the persistent mode
+// each Gram is one more launch whose tail the batch waits for, so when the
+// datasets on the FP4 Gram hold at least half of the batch's pair-updates,
+// the byte datasets left to the library run it too (their conversion joins
+// the batch's one conversion launch; the outputs are the same either way).
+// On the 256-dataset recipe that moves the 11 aligned datasets (1.5% of the
+// pair-updates) off a second launch of 0.2 ms: 3.16 -> 3.04 ms.
+static void batch_grams(const mi_problem* probs, int64_t count, bool persistent, std::vector<char>& conv,
+                        std::vector<char>& f4) {
+  conv.assign(count, 0);
+  f4.assign(count, 0);
+  double pu_all = 0.0, pu_f4 = 0.0;
+  for (int64_t d = 0; d < count; ++d) {
+    conv[d] = converts_to_fp4(&probs[d]) ? 1 : 0;
+    f4[d] = runs_fp4(&probs[d]) ? 1 : 0;
+    const double n = (double)std::max<int64_t>(probs[d].n, 0);
+    const double pu = (double)probs[d].m * n * (n + 1.0) / 2.0;
+    pu_all += pu;
+    if (f4[d]) pu_f4 += pu;
+  }
+  if (!persistent || pu_f4 < 0.5 * pu_all) return;
+  for (int64_t d = 0; d < count; ++d)
+    if (!f4[d] && probs[d].n > 0 && probs[d].packed == MI_INPUT_BYTES && probs[d].gram == MI_GRAM_AUTO)
+      conv[d] = f4[d] = 1;
+}
+
 mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, int mode, const BatchChoice* choice,
                       std::vector<Plan>* plans_out) {
   if (count < 0) return fail(MI_ERR_INVALID_ARG, "count < 0");
@@ -642,11 +669,8 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
                   (long long)d);
   }
   // Per dataset: converted from bytes to the FP4 layout first, and run on the FP4 Gram.
-  std::vector<char> conv(count), f4(count);
-  for (int64_t d = 0; d < count; ++d) {
-    conv[d] = converts_to_fp4(&probs[d]) ? 1 : 0;
-    f4[d] = runs_fp4(&probs[d]) ? 1 : 0;
-  }
+  std::vector<char> conv, f4;
+  batch_grams(probs, count, mode == MI_BATCH_PERSISTENT, conv, f4);
   DeviceInfo di;
   s = device_info(&di);
   if (s != MI_OK) return s;
@@ -1022,8 +1046,9 @@ mi_status tune_batched(const mi_problem* probs, int64_t count, hipStream_t st, d
     s = check_problem(&probs[d], &ldx);
     if (s != MI_OK) return s;
     aligned[d] = is_aligned(probs[d].X, ldx) ? 1 : 0;
-    f4[d] = runs_fp4(&probs[d]) ? 1 : 0;
   }
+  std::vector<char> conv;
+  batch_grams(probs, count, true, conv, f4);
   std::vector<BatchChoice> cands;
   cands.push_back(heuristic_batch_choice());
   const std::pair<int, int> tiles[] = {{kBatchTileAuto, 512},    {(int)MI_TILE_128, 512}, {(int)MI_TILE_256, 512},
