@@ -221,6 +221,20 @@ static int heuristic_splits(int64_t m, const Plan& p1, int cus, double rows_per_
       best = (int)s;
     }
   }
+  // 128-wide tiles fit two workgroups on a CU, and split units that share a
+  // CU measured slower than fewer, longer units each on a CU of its own:
+  // at most one unit per CU, and for short units (under 32,768 rows) at most
+  // 7/8 of the CUs.  Measured (ms, heuristic before -> with these caps):
+  // 1,000,000 x 1,024 1.213 -> 0.930 (19 -> 6 splits; 5: 1.000),
+  // 100,000 x 1,024 0.123 -> 0.105 (6 -> 5), 100,000 x 1,400 on the FP4
+  // Gram 0.240 -> 0.197 (7 -> 3), 100,000 x 512 0.085 -> 0.082 (16 -> 14),
+  // 200,000 x 768 0.138 against 0.140 (10 -> 9); 300,000 x 1,024 keeps 6
+  // (0.300; 5: 0.320).
+  if (p1.bt == 128) {
+    while (best > 1 && 8 * (int64_t)p1.tpx * best > cus) --best;
+    if (cdiv(p1.ksteps, best) * KT < 32768)
+      while (best > 1 && 64 * (int64_t)p1.tpx * best > 7 * (int64_t)cus) --best;
+  }
   return best;
 }
 
