@@ -141,3 +141,30 @@ def test_batched_counts_only_problems(mode):
             assert torch.equal(outs[k], o[0])
         else:
             assert torch.isnan(outs[k]).all()       # untouched
+
+
+def test_batched_wide_unaligned_and_aligned_share_one_gram():
+    """A persistent batch whose unaligned datasets (converted to FP4, one of
+    them with rows of several 64-chunk steps) hold most of the work runs its
+    aligned byte datasets on the FP4 Gram too: bitwise the sequential mode's
+    outputs (each dataset on its own choice), and the oracle's."""
+    say("[batched] wide unaligned rows with aligned datasets")
+    base = synth.generate(synth.spec_random(43, 4000, 2600, 0.02, 0.5), device=DEV)
+    Xs = [
+        base[:, 5:2505],                      # unaligned, 2,500 columns: 79 chunks per converted row
+        base[:2000, 1:1201],                  # unaligned, 1,200 columns
+        synth.generate(synth.spec_random(44, 900, 256, 0.0, 0.8), device=DEV),    # aligned, small
+        synth.generate(synth.spec_random(45, 1200, 64, 0.0, 0.8), device=DEV),    # aligned, narrow
+    ]
+    specs = [type("S", (), {"n": X.shape[1], "m": X.shape[0]})() for X in Xs]
+    seq = _run(specs, Xs, mi.MI_BATCH_SEQUENTIAL)
+    per = _run(specs, Xs, mi.MI_BATCH_PERSISTENT)
+    for k in range(3):
+        assert _equal(seq[k], per[k])
+    for d in (2, 3):
+        X = Xs[d]
+        n = X.shape[1]
+        compare_full(X.cpu().numpy(), n, per[0][d].cpu().numpy(), per[1][d].cpu().numpy(), per[2][d].cpu().numpy()[:n])
+    cols = [0, 1, 127, 128, 1023, 1024, 2047, 2048, 2499]
+    compare_columns(Xs[0][:, cols].cpu().numpy(), cols, per[0][0].cpu().numpy(), per[1][0].cpu().numpy(),
+                    per[2][0].cpu().numpy())

@@ -302,3 +302,25 @@ def test_every_base_offset_and_ragged_width(offset):
         if n % 2:
             nz = np.concatenate([nz, np.zeros((m, 1), np.uint8)], axis=1)
         assert np.array_equal(Q.cpu().numpy()[:, :(n + 1) // 2], (nz[:, 0::2] | (nz[:, 1::2] << 4)).astype(np.uint8))
+
+
+@pytest.mark.parametrize("offset", [1, 7, 13])
+def test_wide_unaligned_rows(offset):
+    """Unaligned layouts with rows of more than 64 16-byte chunks after the
+    conversion or repack (several steps of 64 chunks per row, the last one
+    partly past the row), over enough rows that each wave takes several
+    rounds of items: bitwise the aligned copy's outputs on both Grams, and
+    the oracle's."""
+    rng = np.random.default_rng(900 + offset)
+    for m, n, pitch in ((300, 2500, 2517), (1500, 1100, 1113), (5000, 2085, 2093)):
+        say(f"[wide offset] {offset} m={m} n={n} pitch={pitch}")
+        buf = torch.from_numpy((rng.random((m * pitch + offset + 64,)) < 0.2).astype(np.uint8)).to(DEV)
+        X = buf[offset:offset + m * pitch].view(m, pitch)[:, :n]
+        ref = X.contiguous()
+        for gram in (mi.MI_GRAM_INT8, mi.MI_GRAM_FP4):
+            a = run_gpu(X, gram=gram)
+            b = run_gpu(ref, gram=gram)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (offset, m, n, pitch, gram)
+        if m * n <= 1_000_000:
+            compare_full(ref.cpu().numpy(), n, *run_gpu(X))
