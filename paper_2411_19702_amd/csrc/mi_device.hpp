@@ -944,13 +944,13 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
                        : reinterpret_cast<float*>(wave == 0 ? sm.slot[0] : (wave == 1 ? sm.slot[1] : (wave == 2 ? sm.slot[2] : sm.slot[3])));
   // Evaluate and store accumulator block rows [A0, A0 + 2).  The epilogue
   // mode and the block test are template arguments, so the FP32 path carries
-  // neither mode tests nor bounds tests; the sparse output goes with the
-  // tested path only.  A scheduling barrier after each group of four rows
+  // neither mode tests nor bounds tests (the sparse output's too).  A scheduling barrier after each group of four rows
   // keeps the compiler from hoisting later groups' loads and arithmetic,
   // whose registers on top of the live accumulators would spill.
-  auto emit_rows = [&](auto A0, auto EPI, auto FULL) {
+  auto emit_rows = [&](auto A0, auto EPI, auto FULL, auto PAIRS) {
     constexpr int epi = decltype(EPI)::value;
     constexpr bool fast = decltype(FULL)::value;
+    constexpr bool pairs = decltype(PAIRS)::value;  // the sparse output's code is compiled in
 #pragma unroll
     for (int a = decltype(A0)::value; a < decltype(A0)::value + 2 && a < FM; ++a) {
       if (ibase + blk_a(a) * 32 >= n) continue;  // block rows past n (uniform)
@@ -1010,13 +1010,13 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
               }
             }
           }
-          if (!fast && P.pairs) {
+          if (pairs && P.pairs) {
             // Sparse output: pairs i < j at or above the threshold, one
             // atomic per wave and register.
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const int i = i0 + q;
-              const bool sel = i < n && j < n && j > i && v[q] >= P.thr;
+              const bool sel = (fast || (i < n && j < n && j > i)) && v[q] >= P.thr;
               const unsigned long long mask = __ballot(sel);
               if (mask) {  // uniform
                 const int leader = __ffsll((long long)mask) - 1;
@@ -1076,20 +1076,22 @@ __device__ __forceinline__ void run_unit(const ProbDev& P, int t, int k0, int k1
       }
     }
   };
-  // The FP32 and counts-only modes have both paths; the FP64 modes, and
-  // every block of a problem with the sparse output, take the tested one.
-  const bool fast = full && !P.pairs;
+  // The FP32 and counts-only modes have both paths; the FP64 modes take the
+  // tested one.  The FP32 fast path is compiled twice, with and without the
+  // sparse output's code (which costs the dense path 1.5% when compiled in).
+  const bool fast = full;
   auto rows_mode = [&](auto A0) {
     switch (P.epi) {
       case 0:
-        if (fast) emit_rows(A0, std::integral_constant<int, 0>{}, std::true_type{});
-        else emit_rows(A0, std::integral_constant<int, 0>{}, std::false_type{});
+        if (fast && P.pairs) emit_rows(A0, std::integral_constant<int, 0>{}, std::true_type{}, std::true_type{});
+        else if (fast) emit_rows(A0, std::integral_constant<int, 0>{}, std::true_type{}, std::false_type{});
+        else emit_rows(A0, std::integral_constant<int, 0>{}, std::false_type{}, std::true_type{});
         break;
-      case 1: emit_rows(A0, std::integral_constant<int, 1>{}, std::false_type{}); break;
-      case 2: emit_rows(A0, std::integral_constant<int, 2>{}, std::false_type{}); break;
-      default:
-        if (fast) emit_rows(A0, std::integral_constant<int, kEpiCounts>{}, std::true_type{});
-        else emit_rows(A0, std::integral_constant<int, kEpiCounts>{}, std::false_type{});
+      case 1: emit_rows(A0, std::integral_constant<int, 1>{}, std::false_type{}, std::true_type{}); break;
+      case 2: emit_rows(A0, std::integral_constant<int, 2>{}, std::false_type{}, std::true_type{}); break;
+      default:  // counts only: no MI, no sparse output
+        if (fast) emit_rows(A0, std::integral_constant<int, kEpiCounts>{}, std::true_type{}, std::false_type{});
+        else emit_rows(A0, std::integral_constant<int, kEpiCounts>{}, std::false_type{}, std::false_type{});
         break;
     }
   };
