@@ -399,7 +399,7 @@ def bench_library_gemm(dev, reps: int = 10):
     return res
 
 
-def bench_batched(dev, reps: int = 3):
+def bench_batched(dev, reps: int = 10):
     """256 independent datasets: one persistent launch vs a replayed hipGraph
     of plain launches vs 256 sequential plain calls (same results, bitwise)."""
     import torch
@@ -407,7 +407,8 @@ def bench_batched(dev, reps: int = 3):
     specs = synth.specs_batched()
     Xs = [synth.generate(s, device=dev) for s in specs]
     outs = [torch.empty((s.n, s.n), dtype=torch.float32, device=dev) for s in specs]
-    probs = [mi.make_problem(X, o) for X, o in zip(Xs, outs)]
+    # The batch as one C array of problems, built once (as a C caller would).
+    probs = mi.problem_array([mi.make_problem(X, o) for X, o in zip(Xs, outs)])
     pu = sum(s.m * s.n * (s.n + 1) / 2 for s in specs)
     res = {"workload": "batched_256 (m log-uniform [500, 50000], n U[64, 2048])", "datasets": len(specs),
            "pair_updates": pu}

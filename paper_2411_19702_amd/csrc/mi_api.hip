@@ -825,19 +825,29 @@ mi_status run_batched(const mi_problem* probs, int64_t count, hipStream_t st, in
   constexpr int kLists = 2 * kNumCfg;
   const int order[kLists] = {kNumCfg + 1, kNumCfg + 0, 1, 0};
   static_assert(kNumCfg == 2, "launch order lists every (Gram, tile) pair");
-  std::vector<UnitRef> units[kLists];
+  // The units of one (dataset, split) share their row count, so the groups
+  // are sorted (stably, in dataset and split order) and then expanded tile
+  // by tile: the order of sorting every unit, at the cost of sorting the
+  // groups.
+  struct Group {
+    int64_t rows;
+    int32_t prob, split;
+  };
+  std::vector<Group> groups[kLists];
   for (int64_t d = 0; d < count; ++d) {
     if (probs[d].n == 0) continue;
     const int li = (f4[d] ? kNumCfg : 0) + plans[d].cfg;
     for (int sp = 0; sp < plans[d].splits; ++sp)
-      for (int t = 0; t < plans[d].ntiles; ++t) units[li].push_back(UnitRef{(int32_t)d, t, sp, 0});
+      groups[li].push_back(Group{std::min<int64_t>(P[d].kchunk, P[d].m - (int64_t)sp * P[d].kchunk), (int32_t)d, sp});
   }
+  std::vector<UnitRef> units[kLists];
   for (int c = 0; c < kLists; ++c) {
-    std::stable_sort(units[c].begin(), units[c].end(), [&](const UnitRef& x, const UnitRef& y) {
-      const int64_t rx = std::min<int64_t>(P[x.prob].kchunk, P[x.prob].m - (int64_t)x.split * P[x.prob].kchunk);
-      const int64_t ry = std::min<int64_t>(P[y.prob].kchunk, P[y.prob].m - (int64_t)y.split * P[y.prob].kchunk);
-      return rx > ry;
-    });
+    std::stable_sort(groups[c].begin(), groups[c].end(), [](const Group& x, const Group& y) { return x.rows > y.rows; });
+    size_t nu = 0;
+    for (const Group& g : groups[c]) nu += (size_t)plans[g.prob].ntiles;
+    units[c].reserve(nu);
+    for (const Group& g : groups[c])
+      for (int t = 0; t < plans[g.prob].ntiles; ++t) units[c].push_back(UnitRef{g.prob, t, g.split, 0});
   }
   const size_t probs_bytes = ((sizeof(ProbDev) * count) + 255) & ~(size_t)255;
   size_t nunits = 0;

@@ -292,9 +292,22 @@ def mi_all_pairs_noalloc(X: torch.Tensor, out: Optional[torch.Tensor] = None, n:
     return out
 
 
-def mi_all_pairs_batched(problems: Sequence[mi_problem], mode: int = MI_BATCH_PERSISTENT, stream=None) -> None:
+def problem_array(problems: Sequence[mi_problem]) -> ctypes.Array:
+    """The problems as one C array (what the batched calls take), built once
+    for a batch that is run repeatedly; it keeps the problems' tensors alive."""
     arr = (mi_problem * len(problems))(*problems)
-    _check(lib().mi_all_pairs_batched(arr, len(problems), _stream_handle(stream), int(mode)))
+    arr._keep = [getattr(p, "_keep", None) for p in problems]
+    return arr
+
+
+def _as_array(problems) -> ctypes.Array:
+    return problems if isinstance(problems, ctypes.Array) else problem_array(problems)
+
+
+def mi_all_pairs_batched(problems, mode: int = MI_BATCH_PERSISTENT, stream=None) -> None:
+    """problems: a sequence of make_problem results, or problem_array() of one."""
+    arr = _as_array(problems)
+    _check(lib().mi_all_pairs_batched(arr, len(arr), _stream_handle(stream), int(mode)))
 
 
 def mi_plan(m: int, n: int, ldx: int = 0) -> Tuple[int, int]:
@@ -318,18 +331,18 @@ def mi_tune(m: int, n: int, ldx: int = 0) -> Tuple[int, int, float]:
     return t.value, s.value, ms.value
 
 
-def mi_tune_batched(problems: Sequence[mi_problem], stream=None) -> Tuple[float, float]:
+def mi_tune_batched(problems, stream=None) -> Tuple[float, float]:
     """Tune the persistent plan of this batch on its own data; returns (chosen ms, heuristic ms)."""
-    arr = (mi_problem * len(problems))(*problems)
+    arr = _as_array(problems)
     best, heur = ctypes.c_double(), ctypes.c_double()
-    _check(lib().mi_tune_batched(arr, len(problems), _stream_handle(stream), ctypes.byref(best), ctypes.byref(heur)))
+    _check(lib().mi_tune_batched(arr, len(arr), _stream_handle(stream), ctypes.byref(best), ctypes.byref(heur)))
     return best.value, heur.value
 
 
-def mi_plan_batched(problems: Sequence[mi_problem]) -> Tuple[List[int], List[int]]:
+def mi_plan_batched(problems) -> Tuple[List[int], List[int]]:
     """(tiles, splits) per dataset of the persistent mode's plan for this batch."""
-    k = len(problems)
-    arr = (mi_problem * k)(*problems)
+    arr = _as_array(problems)
+    k = len(arr)
     tiles, splits = (ctypes.c_int32 * max(k, 1))(), (ctypes.c_int32 * max(k, 1))()
     _check(lib().mi_plan_batched(arr, k, ctypes.cast(tiles, ctypes.c_void_p), ctypes.cast(splits, ctypes.c_void_p)))
     return list(tiles)[:k], list(splits)[:k]
