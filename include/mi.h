@@ -179,9 +179,12 @@ mi_status mi_all_pairs_async(const uint8_t* X, int64_t m, int64_t n, float* out,
 mi_status mi_all_pairs_ex(const mi_problem* p, void* stream);
 
 /* Many independent datasets in one call, asynchronous on `stream`.
- *   mode MI_BATCH_PERSISTENT: one persistent launch (per tile configuration
- *        when tiles are forced) pulls (dataset, tile, split) work units from
- *        a device queue, after one launch that repacks every unaligned input;
+ *   mode MI_BATCH_PERSISTENT: one persistent launch per (tile configuration,
+ *        Gram) pulls (dataset, tile, split) work units from a device queue,
+ *        after one launch that converts (or repacks) every input that needs
+ *        it.  When the datasets on the FP4 Gram hold at least half of the
+ *        batch's pair-updates, byte datasets left to MI_GRAM_AUTO run the
+ *        FP4 Gram too (one Gram, one launch; the outputs do not change);
  *   mode MI_BATCH_GRAPH: `count` plain launches captured once into a hipGraph
  *        and replayed (the graph is cached for identical batches);
  *   mode MI_BATCH_SEQUENTIAL: `count` plain launches, one after another.
