@@ -274,3 +274,33 @@ def test_noalloc_argument_checks(L):
     assert na(gram=mi.MI_GRAM_FP4) == 1 and b"FP4" in L.mi_last_error()
     assert na(algo=mi.MI_ALGO_SPARSE) == 1 and na(algo=mi.MI_ALGO_AUTO) == 1
     assert na(n=0) == 0                                         # no-op, no device work
+
+
+def test_problem_array_keeps_its_tensors_and_passes_through():
+    """problem_array copies the problems into one C array and keeps every
+    problem's tensors referenced; the batched calls take it as it is."""
+    import gc
+    import weakref
+
+    from paper_2411_19702_amd import mi
+
+    class Held:  # stands in for a tensor a problem points to
+        pass
+
+    held = [Held() for _ in range(3)]
+    refs = [weakref.ref(h) for h in held]
+    probs = []
+    for k, h in enumerate(held):
+        p = mi.mi_problem()
+        p.m, p.n = 10 + k, 4
+        p._keep = (h,)
+        probs.append(p)
+    arr = mi.problem_array(probs)
+    del probs, held, p, h
+    gc.collect()
+    assert all(r() is not None for r in refs)
+    assert isinstance(arr, ctypes.Array) and len(arr) == 3 and [a.m for a in arr] == [10, 11, 12]
+    assert mi._as_array(arr) is arr
+    del arr
+    gc.collect()
+    assert all(r() is None for r in refs)
